@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: LocalPower local-iteration throughput on one MI355X.
+
+Workload (the FP32 fused-path configuration): A is 262144 x 1024 FP32,
+low-rank-plus-noise with a spectral gap sigma_16/sigma_17 = 1.2, k = 16,
+m = 32 equal partitions, p = 4, T = 50 rounds, sign-fixing.  One step is one
+full lp_run (50 rounds = 200 local iterations on every partition, with the
+local orthonormalisations, alignments, aggregations and global orths).
+
+value  = algorithmic bytes of A streamed per step (200 * n * d * 4) / step time.
+roofline.achieved = n * d * 4 bytes / average duration of one local-multiply
+launch (HIP events around each launch on the library's stream, inside the
+timed steps).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "local-iter GB/s (% HBM peak); rounds to sinθ≤1e-6; jobs/s + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "local_multiply_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2002_08014_amd", "csrc", f)
+                  for f in ("k_local.hip", "k_mfma.hip")]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        if os.path.exists(f):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per local-multiply launch from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(A_dev, offsets, k, Y0, budget_s=12.0):
+    """The FP64 oracle on a bounded sample: the first 4 partitions, one round of
+    p = 4 local iterations repeated until the time budget is used."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    parts = 4
+    rows = int(offsets[parts])
+    A = A_dev[:rows].to("cpu").to(torch.float64).numpy()
+    sub = np.asarray(offsets[:parts + 1])
+    d = A.shape[1]
+    iters = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.localpower(A, sub, k, [4], "sign", Y0)
+        iters += 4
+    el = time.perf_counter() - t0
+    gbs = iters * rows * d * 4 / el / 1e9
+    return {"value": gbs, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"first {parts} of 32 partitions ({rows}x{d} upcast to FP64), "
+                      f"{iters // 4} rounds of p=4 sign-fixing in {el:.1f} s; bytes counted as FP32 "
+                      f"storage like the GPU figure"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rounds", type=int, default=50)
+    ap.add_argument("--mode", default="sign", choices=["sign", "opt", "vanilla"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the m LocalPower nodes are partitions on a single "
+              f"device, so --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import synth
+    import paper_2002_08014_amd as lp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating A 262144x1024 fp32 on the GPU")
+    w = synth.make_c2(device=dev, mode=args.mode, rounds=args.rounds)
+    n, d, k = w.n, w.d, w.k
+    torch.cuda.synchronize()
+    P = lp.lp_create(w.A, w.offsets, k)
+    sched = w.p_sched
+    iters_per_step = int(sum(sched))
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        lp.lp_run(P, k, sched, args.mode, w.Y0, time_local=True)
+    torch.cuda.synchronize()
+    log(f"timed x{args.steps}")
+    ms_local, launches = 0.0, 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = lp.lp_run(P, k, sched, args.mode, w.Y0, time_local=True)
+        ms_local += r["stats"]["ms_local"]
+        launches += r["stats"]["local_launches"]
+        log(f"step {i} done")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    bytes_iter = n * d * w.A.element_size()
+    value = args.steps * iters_per_step * bytes_iter / el / 1e9
+    k1_ms = ms_local / max(launches, 1)
+    achieved = bytes_iter / (k1_ms / 1e3) / 1e9
+    traffic = traffic_per_launch()
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"localpower fp32 A {n}x{d}, k={k}, m={w.m} equal partitions, "
+                               f"p=4, T={len(sched)} rounds, {args.mode} alignment",
+                   "n": n, "d": d, "k": k, "m": w.m, "p": 4, "rounds": len(sched),
+                   "local_iters_per_step": iters_per_step, "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel_ms": round(k1_ms, 5), "launches": launches},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a sample)")
+        out["cpu_baseline"] = cpu_baseline(w.A, w.offsets, k, w.Y0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

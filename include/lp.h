@@ -1,0 +1,172 @@
+/*
+ * lp.h -- C ABI of the MI355X LocalPower library (liblp.so).
+ *
+ * LocalPower (Li, Wang, Chen, Zhang, "Communication-Efficient Distributed SVD
+ * via Local Power Iterations", Algorithm 1) computes an orthonormal basis Z
+ * (d x k) of the top-k right singular subspace of a row-partitioned matrix
+ * A = [A_1; ...; A_m] (A_i is s_i x d).  Every communication round each of the
+ * m partitions ("nodes") runs p local power iterations
+ *     Y_i = M_i Z_i,  M_i = A_i^T A_i / s_i          (Eq. (power_yi))
+ *     Z_i = orth(Y_i)                                   (between local steps)
+ * then the inputs of the last local step are aligned against the base node
+ * (sign-fixing, Eq. (opt:d), or orthogonal Procrustes, Eq. (opt:o)) and the
+ * server aggregates Y = sum_i (s_i/n) Y_i D_i and orthonormalises it.
+ * All m nodes run on one GPU; a "round" is one aggregation.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns lp_status; nothing throws or aborts across the ABI.
+ *     lp_last_error() returns a thread-local description of the last failure.
+ *   - "device" pointers are GPU memory of the current HIP device; "host"
+ *     pointers are CPU memory.  Matrices are row-major with the stated leading
+ *     dimension; d x k matrices are dense (leading dimension k).
+ *   - Inputs are BORROWED (the caller keeps them alive while in use); outputs
+ *     are caller-owned.  The library allocates no device memory: all scratch
+ *     lives in the workspace the caller passes to lp_create.
+ *   - All GPU work is enqueued on the stream given to lp_create (a hipStream_t;
+ *     NULL means the legacy default stream); calls that return host results
+ *     synchronise that stream before returning.
+ *   - orth(Y) is the Q factor of the thin QR Y = QR with positive diagonal R
+ *     (computed by CholeskyQR2 in FP64), the unique choice of the paper's
+ *     "QR factorisation" orth.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LP_OK = 0,
+  LP_EINVAL = -1,      /* invalid argument (see the entry point's contract) */
+  LP_ENOMEM = -2,      /* workspace too small / admission refused for memory */
+  LP_EDEVICE = -3,     /* a HIP call failed */
+  LP_EBREAKDOWN = -4,  /* Cholesky of a Gram matrix broke down (rank-deficient iterate) */
+  LP_ENOTCONV = -5,    /* a stop target was not reached within max_rounds */
+  LP_EBUSY = -6        /* resource busy (no free serving slot) */
+} lp_status;
+
+typedef enum { LP_F64 = 0, LP_F32 = 1, LP_BF16 = 2 } lp_dtype;
+
+/* Alignment of the local iterates before aggregation: the set F of the
+ * unified update rule (Eq. (D0)): {I} (vanilla), D_k (sign-fixing, Eq.
+ * (opt:d)), O_k (orthogonal Procrustes, Eq. (opt:o)). */
+typedef enum { LP_AGG_VANILLA = 0, LP_AGG_SIGN = 1, LP_AGG_OPT = 2 } lp_agg;
+
+typedef struct lp_problem lp_problem; /* opaque */
+
+const char* lp_strerror(lp_status s);
+const char* lp_last_error(void);
+
+/* Bytes of device workspace lp_create needs for this problem.
+ *   dtype, n, d : storage type and shape of A (n rows = samples, d columns);
+ *   offsets     : host int64[m+1], offsets[0] = 0, offsets[m] = n, strictly
+ *                 increasing: partition i is rows [offsets[i], offsets[i+1]);
+ *   k_max       : the largest k any later lp_run will use (1 <= k_max <= d).
+ * Writes the byte count to *bytes.  LP_EINVAL on inconsistent arguments. */
+lp_status lp_workspace_size(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets,
+                            int32_t m, int32_t k_max, size_t* bytes);
+
+/* Create a problem over a row-partitioned matrix (Section 2, data parallelism:
+ * the rows of A are split into m contiguous partitions, one per node).
+ *   A          : device, n x d row-major with leading dimension lda >= d,
+ *                16-byte aligned, element type `dtype`; BORROWED until
+ *                lp_destroy.  FP32/BF16 values are multiplied with FP32
+ *                accumulation, FP64 values in FP64.
+ *   offsets    : host int64[m+1] as for lp_workspace_size; COPIED.
+ *   workspace  : device, >= lp_workspace_size(...) bytes, 256-byte aligned;
+ *                BORROWED until lp_destroy.
+ *   stream     : hipStream_t on which all work of this problem is enqueued.
+ * The base node (the alignment target) is the partition with the most rows,
+ * lowest index on ties.  LP_EINVAL for bad shapes/offsets/alignment, LP_ENOMEM
+ * when ws_bytes is too small. */
+lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, int64_t d,
+                    int64_t lda, const int64_t* offsets, int32_t m, int32_t k_max,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+lp_status lp_destroy(lp_problem* P);
+
+/* Options of lp_run; zero-initialise and set struct_size = sizeof(lp_run_opts). */
+typedef struct {
+  int32_t struct_size;
+  const double* U_ref;  /* device d x k FP64 orthonormal reference or NULL */
+  double* sin_hist;     /* host [T]: sin theta_k(Z_r, U_ref) after each round, or NULL */
+  int8_t* signs_out;    /* host [T*m*k]: sign-fixing decisions (+1/-1) per round, 0 where
+                           the round used none (p = 1 or another mode); or NULL */
+  int32_t z0_orthonormal; /* 1: Y0 is already orthonormal and is used as Z_0 as is
+                             (resume from a saved round); 0: Z_0 = orth(Y0) */
+  int32_t use_graph;    /* 1 (default when struct_size covers it and it is 1): replay each
+                           round shape as a captured hipGraph; 0: plain launches */
+  int32_t time_local;   /* 1: bracket every local-multiply launch with a pair of HIP events
+                           on the problem's stream and report their summed duration in
+                           stats->ms_local (forces plain launches) */
+} lp_run_opts;
+
+typedef struct {
+  int32_t rounds;          /* communication rounds completed */
+  int32_t local_iters;     /* local power iterations per node completed */
+  int32_t breakdowns;      /* Cholesky breakdowns detected (0 on success) */
+  int32_t near_singular;   /* OPT alignments whose Z_i^T Z_b had sigma_min < 1e-12 sigma_max */
+  double ms_total;         /* duration of the rounds on the stream (HIP events) */
+  double bytes_A;          /* algorithmic bytes of A streamed: local_iters * n * d * elem */
+  double ms_local;         /* with opts->time_local: summed duration of the local-multiply
+                              launches (HIP events), else 0 */
+  int32_t local_launches;  /* local-multiply launches timed into ms_local */
+  int32_t reserved;
+} lp_run_stats;
+
+/* Run LocalPower (Algorithm 1) for T communication rounds.
+ *   k       : target = iteration rank, 1 <= k <= k_max, k <= every s_i.
+ *   p_sched : host int32[T], p_sched[r] >= 1 local iterations in round r (fixed p,
+ *             a decaying schedule, or p = T total for one-shot); COPIED.
+ *   mode    : alignment used when p_sched[r] >= 2 (rounds with p = 1 use none).
+ *   Y0      : device d x k FP64 start matrix (the Gaussian Y_0 of Algorithm 1);
+ *             Z_0 = orth(Y0) unless opts->z0_orthonormal.
+ *   Z_out   : device d x k FP64, receives Z_T = orth(aggregate of the last round).
+ *   ritz_out: device [k] FP64 or NULL: when given, one extra p = 1 pass forms
+ *             H = Z^T M Z, Z_out is rotated to its eigenvectors and ritz_out gets the
+ *             Ritz values (eigenvalues of M = A^T A / n) in descending order.
+ *   opts, stats : may be NULL.
+ * Synchronises the stream before returning.  On LP_EBREAKDOWN Z_out holds the last
+ * valid Z and stats->rounds how many rounds completed. */
+lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp_agg mode,
+                 const double* Y0, double* Z_out, double* ritz_out, const lp_run_opts* opts,
+                 lp_run_stats* stats);
+
+/* One local power iteration on every partition with a shared Z (the worker step
+ * of DPI, Eq. (power_yi), without the 1/s_i scale):
+ *   Z     : device d x k FP64 (rounded to the working precision of A's dtype);
+ *   Y_out : device m x d x k FP64, Y_out[i] = A_i^T (A_i Z).
+ * Enqueued on the problem's stream; asynchronous. */
+lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y_out);
+
+/* Batched orth: Q_b = orth(Y_b) for b < batch, each d x k FP64 (CholeskyQR2).
+ *   Y, Q : device, batch * d * k FP64 (may alias);  flags: device int32[batch]
+ *   or NULL, set to 1 where a Cholesky broke down.  Uses the problem's workspace and
+ *   stream; requires d == the problem's d, k <= k_max, batch <= max(m, 1). */
+lp_status lp_orth(lp_problem* P, int32_t k, int32_t batch, const double* Y, double* Q,
+                  int32_t* flags);
+
+/* Alignment of batch iterates Zi (device, batch x d x k FP64) against Zb (device
+ * d x k FP64):
+ *   LP_AGG_SIGN: out is device int8[batch*k], sgn(<Zi[:,j], Zb[:,j]>) with sgn(0)=+1;
+ *   LP_AGG_OPT : out is device FP64 [batch*k*k], O_i = W1 W2^T from the SVD
+ *                W1 S W2^T = Zi^T Zb (one-sided Jacobi, FP64).
+ * Same workspace/stream rules as lp_orth. */
+lp_status lp_align(lp_problem* P, int32_t k, int32_t batch, lp_agg mode, const double* Zi,
+                   const double* Zb, void* out);
+
+/* sin theta_k(Z, U) = ||U - Z (Z^T U)||_2 (Definition 1), for device d x k FP64
+ * matrices with orthonormal columns.  Uses its own small scratch on the stream
+ * (no workspace), synchronises and writes the result to *out_host. */
+lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

@@ -1,0 +1,19 @@
+"""MI355X-native LocalPower: HIP kernels for gfx950 behind a C ABI (include/lp.h).
+
+The Python layer is a thin ctypes binding (same names as the C entry points);
+PyTorch supplies device memory and streams only.
+"""
+
+from ._lib import (  # noqa: F401
+    LPError,
+    Problem,
+    load,
+    lp_workspace_size,
+    lp_create,
+    lp_destroy,
+    lp_run,
+    lp_local_multiply,
+    lp_orth,
+    lp_align,
+    lp_sin_theta,
+)

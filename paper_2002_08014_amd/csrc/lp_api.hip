@@ -1,0 +1,604 @@
+// C ABI of the LocalPower library: problem handle, workspace layout, the
+// round driver (Algorithm 1 with sign-fixing / OPT alignment) and its hipGraph
+// replay.  Host code only; the kernels live in k_local.hip and k_small.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lp_status fail(lp_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define LP_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t elem_bytes(lp_dtype t) { return t == LP_F64 ? 8 : (t == LP_F32 ? 4 : 2); }
+
+bool check_offsets(const int64_t* o, int32_t m, int64_t n, std::string* err) {
+  if (o == nullptr || m < 1) {
+    *err = "offsets must be non-NULL with m >= 1";
+    return false;
+  }
+  if (o[0] != 0 || o[m] != n) {
+    *err = "offsets[0] must be 0 and offsets[m] must be n";
+    return false;
+  }
+  for (int i = 0; i < m; ++i)
+    if (o[i + 1] <= o[i]) {
+      *err = "offsets must increase strictly (every partition non-empty)";
+      return false;
+    }
+  return true;
+}
+
+}  // namespace
+
+namespace lp {
+
+bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int32_t m,
+               int32_t k_max, Plan* P, std::string* err) {
+  if (dtype != LP_F64 && dtype != LP_F32 && dtype != LP_BF16) {
+    *err = "unknown dtype";
+    return false;
+  }
+  if (n < 1 || d < 1) {
+    *err = "need n >= 1 and d >= 1";
+    return false;
+  }
+  if (k_max < 1 || k_max > kMaxK || k_max > d) {
+    *err = "need 1 <= k_max <= min(d, 64)";
+    return false;
+  }
+  if (!check_offsets(offsets, m, n, err)) return false;
+  P->dtype = dtype;
+  P->n = n;
+  P->d = d;
+  P->m = m;
+  P->k_max = k_max;
+  P->acc_bytes = dtype == LP_F64 ? 8 : 4;
+  P->zw_bytes = dtype == LP_F64 ? 8 : 4;
+  P->path = LocalPath::TwoPass;
+  // about 1024 work items over the whole matrix, 64-row granularity
+  int64_t cr = (n + 1023) / 1024;
+  cr = ((cr + 63) / 64) * 64;
+  cr = std::max<int64_t>(64, std::min<int64_t>(cr, 4096));
+  P->chunk_rows = cr;
+  P->items.clear();
+  int32_t slot = 0;
+  for (int i = 0; i < m; ++i) {
+    for (int64_t r = offsets[i]; r < offsets[i + 1]; r += cr) {
+      WorkItem it;
+      it.part = i;
+      it.slot = slot++;
+      it.row0 = r;
+      it.rows = std::min<int64_t>(cr, offsets[i + 1] - r);
+      P->items.push_back(it);
+    }
+  }
+  P->n_gram_chunks = (int32_t)((d + kGramRows - 1) / kGramRows);
+  const size_t dk = (size_t)d * k_max;
+  const size_t mb = (size_t)std::max(m, 1);
+  Layout& L = P->L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.Zi = take(mb * dk * 8);
+  L.Zw = take(mb * dk * P->zw_bytes);
+  L.Yi = take(mb * dk * 8);
+  L.tmp = take(mb * dk * 8);
+  L.Z = take(dk * 8);
+  L.Zw_shared = take(dk * P->zw_bytes);
+  L.Y = take(dk * 8);
+  L.Uref = take(dk * 8);
+  L.part = take(P->items.size() * dk * P->acc_bytes);
+  L.tbuf = take((size_t)n * k_max * P->acc_bytes);
+  L.gram = take(mb * P->n_gram_chunks * (size_t)k_max * k_max * 8);
+  L.rinv = take(mb * (size_t)k_max * k_max * 8);
+  L.omat = take(mb * (size_t)k_max * k_max * 8);
+  L.sgn = take(mb * k_max);
+  L.flags = take((mb + 2) * 4);
+  L.items = take(P->items.size() * sizeof(WorkItem));
+  L.slot_off = take((mb + 1) * 4);
+  L.hist = take(kHistCap * 8);
+  L.ctr = take(4);
+  L.scal = take(64 * 8);
+  L.total = o;
+  return true;
+}
+
+hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
+                                 int64_t z_stride, void* tbuf, void* part,
+                                 const WorkItem* items_dev, hipStream_t s) {
+  return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
+}
+
+hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y, double* Q,
+                   void* zw, int32_t* flags, hipStream_t s) {
+  const Layout& L = P.L;
+  double* gram = (double*)(ws + L.gram);
+  double* rinv = (double*)(ws + L.rinv);
+  double* tmp = (double*)(ws + L.tmp);
+  const int nch = (int)((d + kGramRows - 1) / kGramRows);
+  const int64_t dk = d * k;
+  hipError_t e;
+  // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}
+  if ((e = launch_cross_gram(batch, d, k, Y, dk, Y, dk, gram, s)) != hipSuccess) return e;
+  if ((e = launch_chol_inv(batch, nch, k, gram, rinv, flags, s)) != hipSuccess) return e;
+  if ((e = launch_right_mult(batch, d, k, Y, rinv, (int64_t)k * k, true, tmp, nullptr, 0, s)) !=
+      hipSuccess)
+    return e;
+  // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1}
+  if ((e = launch_cross_gram(batch, d, k, tmp, dk, tmp, dk, gram, s)) != hipSuccess) return e;
+  if ((e = launch_chol_inv(batch, nch, k, gram, rinv, flags, s)) != hipSuccess) return e;
+  return launch_right_mult(batch, d, k, tmp, rinv, (int64_t)k * k, true, Q, zw, P.zw_bytes, s);
+}
+
+}  // namespace lp
+
+using namespace lp;
+
+namespace {
+
+struct Ptrs {
+  double *Zi, *Yi, *Z, *Y, *Uref, *gram, *omat, *hist;
+  void *Zw, *Zw_shared, *part, *tbuf;
+  int8_t* sgn;
+  int32_t *flags, *slot_off, *ctr;
+  WorkItem* items;
+};
+
+Ptrs ptrs(lp_problem* P) {
+  const Layout& L = P->plan.L;
+  char* w = P->ws;
+  Ptrs p;
+  p.Zi = (double*)(w + L.Zi);
+  p.Yi = (double*)(w + L.Yi);
+  p.Z = (double*)(w + L.Z);
+  p.Y = (double*)(w + L.Y);
+  p.Uref = (double*)(w + L.Uref);
+  p.gram = (double*)(w + L.gram);
+  p.omat = (double*)(w + L.omat);
+  p.hist = (double*)(w + L.hist);
+  p.Zw = w + L.Zw;
+  p.Zw_shared = w + L.Zw_shared;
+  p.part = w + L.part;
+  p.tbuf = w + L.tbuf;
+  p.sgn = (int8_t*)(w + L.sgn);
+  p.flags = (int32_t*)(w + L.flags);
+  p.slot_off = (int32_t*)(w + L.slot_off);
+  p.ctr = (int32_t*)(w + L.ctr);
+  p.items = (WorkItem*)(w + L.items);
+  return p;
+}
+
+constexpr int kEvPairs = 256;
+
+// Sum the durations of the recorded event pairs into P->ms_local.
+hipError_t drain_timing(lp_problem* P) {
+  if (P->ev_used == 0) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(P->stream);
+  if (e != hipSuccess) return e;
+  for (int j = 0; j < P->ev_used; ++j) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, P->ev_pool[2 * j], P->ev_pool[2 * j + 1]);
+    if (e != hipSuccess) return e;
+    P->ms_local += ms;
+  }
+  P->local_launches += P->ev_used;
+  P->ev_used = 0;
+  return hipSuccess;
+}
+
+// One local iteration on every partition: Yi = A_i^T (A_i Z_i).
+hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
+  Ptrs p = ptrs(P);
+  hipError_t e;
+  const bool timed = P->timing;
+  if (timed) {
+    if (P->ev_used == kEvPairs && (e = drain_timing(P)) != hipSuccess) return e;
+    if ((e = hipEventRecord(P->ev_pool[2 * P->ev_used], P->stream)) != hipSuccess) return e;
+  }
+  e = launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, p.tbuf, p.part, p.items,
+                            P->stream);
+  if (e != hipSuccess) return e;
+  if (timed) {
+    if ((e = hipEventRecord(P->ev_pool[2 * P->ev_used + 1], P->stream)) != hipSuccess) return e;
+    P->ev_used++;
+  }
+  return launch_reduce_partials(P->plan, k, p.part, p.slot_off, p.Yi, P->stream);
+}
+
+// Enqueue one communication round with p local steps (only kernel launches, so
+// the sequence can be captured into a graph).
+hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
+  Ptrs q = ptrs(P);
+  hipStream_t s = P->stream;
+  const int m = P->m;
+  const int64_t d = P->d;
+  const int64_t dk = d * k;
+  const int nch = P->plan.n_gram_chunks;
+  hipError_t e;
+  for (int l = 1; l <= p; ++l) {
+    const void* zsrc = (l == 1) ? q.Zw_shared : q.Zw;
+    const int64_t zstride = (l == 1) ? 0 : dk;
+    if (l == p && p >= 2 && mode != LP_AGG_VANILLA) {
+      // align the inputs of the last local step against the base node's
+      const double* Zb = q.Zi + (int64_t)P->base * dk;
+      if ((e = launch_cross_gram(m, d, k, q.Zi, dk, Zb, 0, q.gram, s)) != hipSuccess) return e;
+      if (mode == LP_AGG_SIGN) {
+        if ((e = launch_sign_from_gram(m, nch, k, q.gram, q.sgn, s)) != hipSuccess) return e;
+        if ((e = launch_apply_signs(m, d, k, q.Zi, q.sgn, q.Zw, P->plan.zw_bytes, s)) != hipSuccess)
+          return e;
+      } else {
+        if ((e = launch_procrustes(m, nch, k, q.gram, q.omat, q.flags + m + 1, s)) != hipSuccess)
+          return e;
+        if ((e = launch_right_mult(m, d, k, q.Zi, q.omat, (int64_t)k * k, false, nullptr, q.Zw,
+                                   P->plan.zw_bytes, s)) != hipSuccess)
+          return e;
+      }
+    }
+    if ((e = local_iter(P, k, zsrc, zstride)) != hipSuccess) return e;
+    if (l < p) {
+      if ((e = cholqr2(P->plan, P->ws, m, d, k, q.Yi, q.Zi, q.Zw, q.flags, s)) != hipSuccess)
+        return e;
+    }
+  }
+  if ((e = launch_aggregate(m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, s)) != hipSuccess) return e;
+  if ((e = cholqr2(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + m, s)) != hipSuccess)
+    return e;
+  if (hist) {
+    if ((e = launch_sin_theta(d, k, q.Z, q.Uref, nullptr, q.hist, q.ctr, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool use_graph) {
+  if (!use_graph) {
+    LP_HIP(enqueue_round(P, k, p, mode, hist));
+    return LP_OK;
+  }
+  GraphKey key{k, p, (int)mode, hist ? 1 : 0};
+  auto it = P->graphs.find(key);
+  if (it == P->graphs.end()) {
+    hipGraph_t g = nullptr;
+    LP_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_round(P, k, p, mode, hist);
+    hipError_t e2 = hipStreamEndCapture(P->stream, &g);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(LP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(LP_EDEVICE, std::string("end capture: ") + hipGetErrorString(e2));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return fail(LP_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e3));
+    it = P->graphs.emplace(key, ex).first;
+  }
+  LP_HIP(hipGraphLaunch(it->second, P->stream));
+  return LP_OK;
+}
+
+// Make the problem's own stream wait for the caller's stream.
+lp_status join_in(lp_problem* P) {
+  LP_HIP(hipEventRecord(P->ev_join_in, P->user_stream));
+  LP_HIP(hipStreamWaitEvent(P->stream, P->ev_join_in, 0));
+  return LP_OK;
+}
+
+// Make the caller's stream wait for the problem's own stream.
+lp_status join_out(lp_problem* P) {
+  LP_HIP(hipEventRecord(P->ev_join_out, P->stream));
+  LP_HIP(hipStreamWaitEvent(P->user_stream, P->ev_join_out, 0));
+  return LP_OK;
+}
+
+lp_status check_k(lp_problem* P, int32_t k) {
+  if (k < 1 || k > P->k_max) return fail(LP_EINVAL, "need 1 <= k <= k_max");
+  for (int i = 0; i < P->m; ++i)
+    if (P->offsets[i + 1] - P->offsets[i] < k)
+      return fail(LP_EINVAL, "every partition needs at least k rows");
+  return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lp_strerror(lp_status s) {
+  switch (s) {
+    case LP_OK: return "ok";
+    case LP_EINVAL: return "invalid argument";
+    case LP_ENOMEM: return "insufficient memory";
+    case LP_EDEVICE: return "HIP device error";
+    case LP_EBREAKDOWN: return "Cholesky breakdown (rank-deficient iterate)";
+    case LP_ENOTCONV: return "not converged";
+    case LP_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* lp_last_error(void) { return g_err.c_str(); }
+
+lp_status lp_workspace_size(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int32_t m,
+                            int32_t k_max, size_t* bytes) {
+  if (bytes == nullptr) return fail(LP_EINVAL, "bytes is NULL");
+  Plan P;
+  std::string err;
+  if (!make_plan(dtype, n, d, offsets, m, k_max, &P, &err)) return fail(LP_EINVAL, err);
+  *bytes = P.L.total;
+  return LP_OK;
+}
+
+lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, int64_t d,
+                    int64_t lda, const int64_t* offsets, int32_t m, int32_t k_max, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  if (out == nullptr) return fail(LP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (A == nullptr) return fail(LP_EINVAL, "A is NULL");
+  if (((uintptr_t)A & 15) != 0) return fail(LP_EINVAL, "A must be 16-byte aligned");
+  if (lda < d) return fail(LP_EINVAL, "need lda >= d");
+  if (workspace == nullptr || ((uintptr_t)workspace & 255) != 0)
+    return fail(LP_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  std::string err;
+  lp_problem* P = new (std::nothrow) lp_problem();
+  if (P == nullptr) return fail(LP_ENOMEM, "host allocation failed");
+  if (!make_plan(dtype, n, d, offsets, m, k_max, &P->plan, &err)) {
+    delete P;
+    return fail(LP_EINVAL, err);
+  }
+  if (ws_bytes < P->plan.L.total) {
+    size_t need = P->plan.L.total;
+    delete P;
+    return fail(LP_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  P->A = A;
+  P->dtype = dtype;
+  P->n = n;
+  P->d = d;
+  P->lda = lda;
+  P->m = m;
+  P->k_max = k_max;
+  P->offsets.assign(offsets, offsets + m + 1);
+  P->base = 0;
+  for (int i = 1; i < m; ++i)
+    if (offsets[i + 1] - offsets[i] > offsets[P->base + 1] - offsets[P->base]) P->base = i;
+  P->ws = (char*)workspace;
+  P->ws_bytes = ws_bytes;
+  P->user_stream = (hipStream_t)stream;
+  hipError_t e = hipGetDevice(&P->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&P->ev_t0);
+  if (e == hipSuccess) e = hipEventCreate(&P->ev_t1);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(LP_EDEVICE, std::string("stream/event creation: ") + hipGetErrorString(e));
+  }
+  // upload the work list and the slot prefix (synchronous, once)
+  std::vector<int32_t> slot_off(m + 1, 0);
+  for (const WorkItem& it : P->plan.items) slot_off[it.part + 1]++;
+  for (int i = 0; i < m; ++i) slot_off[i + 1] += slot_off[i];
+  Ptrs p = ptrs(P);
+  e = hipMemcpyAsync(p.items, P->plan.items.data(), P->plan.items.size() * sizeof(WorkItem),
+                     hipMemcpyHostToDevice, P->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p.slot_off, slot_off.data(), (m + 1) * sizeof(int32_t),
+                       hipMemcpyHostToDevice, P->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+  if (e != hipSuccess) {
+    lp_destroy(P);
+    return fail(LP_EDEVICE, std::string("upload of the work list: ") + hipGetErrorString(e));
+  }
+  *out = P;
+  return LP_OK;
+}
+
+lp_status lp_destroy(lp_problem* P) {
+  if (P == nullptr) return LP_OK;
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& ev : P->ev_pool)
+    if (ev) (void)hipEventDestroy(ev);
+  if (P->stream) {
+    (void)hipStreamSynchronize(P->stream);
+    (void)hipStreamDestroy(P->stream);
+  }
+  if (P->ev_join_in) (void)hipEventDestroy(P->ev_join_in);
+  if (P->ev_join_out) (void)hipEventDestroy(P->ev_join_out);
+  if (P->ev_t0) (void)hipEventDestroy(P->ev_t0);
+  if (P->ev_t1) (void)hipEventDestroy(P->ev_t1);
+  delete P;
+  return LP_OK;
+}
+
+lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp_agg mode,
+                 const double* Y0, double* Z_out, double* ritz_out, const lp_run_opts* opts,
+                 lp_run_stats* stats) {
+  if (P == nullptr) return fail(LP_EINVAL, "problem is NULL");
+  lp_status st = check_k(P, k);
+  if (st != LP_OK) return st;
+  if (T < 1 || p_sched == nullptr) return fail(LP_EINVAL, "need T >= 1 and a schedule");
+  for (int r = 0; r < T; ++r)
+    if (p_sched[r] < 1) return fail(LP_EINVAL, "every p_sched[r] must be >= 1");
+  if (mode != LP_AGG_VANILLA && mode != LP_AGG_SIGN && mode != LP_AGG_OPT)
+    return fail(LP_EINVAL, "unknown aggregation mode");
+  if (Y0 == nullptr || Z_out == nullptr) return fail(LP_EINVAL, "Y0 and Z_out are required");
+  lp_run_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.use_graph = 1;
+  if (opts != nullptr) {
+    const size_t n = std::min<size_t>(sizeof(o), (size_t)std::max(opts->struct_size, 0));
+    std::memcpy(&o, opts, n);
+    if (n < offsetof(lp_run_opts, use_graph) + sizeof(int32_t)) o.use_graph = 1;
+  }
+  const bool hist = o.U_ref != nullptr && o.sin_hist != nullptr;
+  const bool timing = o.time_local != 0;
+  const bool graph = o.use_graph != 0 && !timing;
+  if (timing && P->ev_pool.empty()) {
+    P->ev_pool.assign(2 * kEvPairs, nullptr);
+    for (auto& ev : P->ev_pool) LP_HIP(hipEventCreate(&ev));
+  }
+  P->ev_used = 0;
+  P->ms_local = 0.0;
+  P->local_launches = 0;
+  Ptrs q = ptrs(P);
+  const int m = P->m;
+  const int64_t d = P->d;
+  const int64_t dk = d * k;
+  hipStream_t s = P->stream;
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(launch_fill_i32(q.flags, m + 2, 0, s));
+  LP_HIP(launch_fill_i32(q.ctr, 1, 0, s));
+  if (hist) LP_HIP(hipMemcpyAsync(q.Uref, o.U_ref, dk * 8, hipMemcpyDeviceToDevice, s));
+  // Z_0 = orth(Y_0) (Algorithm 1, initialisation)
+  if (o.z0_orthonormal) {
+    LP_HIP(hipMemcpyAsync(q.Z, Y0, dk * 8, hipMemcpyDeviceToDevice, s));
+    LP_HIP(launch_to_working(P->plan, 1, d, k, q.Z, q.Zw_shared, s));
+  } else {
+    LP_HIP(cholqr2(P->plan, P->ws, 1, d, k, Y0, q.Z, q.Zw_shared, q.flags + m, s));
+  }
+  LP_HIP(hipEventRecord(P->ev_t0, s));
+  int rounds = 0, iters = 0, hist_done = 0;
+  P->timing = timing;
+  for (int r = 0; r < T; ++r) {
+    const int p = p_sched[r];
+    st = run_round(P, k, p, mode, hist, graph);
+    if (st != LP_OK) {
+      P->timing = false;
+      return st;
+    }
+    rounds++;
+    iters += p;
+    if (o.signs_out != nullptr) {
+      int8_t* dst = o.signs_out + (size_t)r * m * k;
+      if (p >= 2 && mode == LP_AGG_SIGN) {
+        LP_HIP(hipMemcpyAsync(dst, q.sgn, (size_t)m * k, hipMemcpyDeviceToHost, s));
+        LP_HIP(hipStreamSynchronize(s));
+      } else {
+        std::memset(dst, 0, (size_t)m * k);
+      }
+    }
+    if (hist && (rounds - hist_done == kHistCap || r == T - 1)) {
+      LP_HIP(hipMemcpyAsync(o.sin_hist + hist_done, q.hist, (size_t)(rounds - hist_done) * 8,
+                            hipMemcpyDeviceToHost, s));
+      LP_HIP(launch_fill_i32(q.ctr, 1, 0, s));
+      LP_HIP(hipStreamSynchronize(s));
+      hist_done = rounds;
+    }
+  }
+  LP_HIP(hipEventRecord(P->ev_t1, s));
+  if (timing) LP_HIP(drain_timing(P));
+  P->timing = false;
+  if (ritz_out != nullptr) {
+    // one p = 1 pass: Y = M Z, H = Z^T Y, H = Q diag(lam) Q^T, Z <- Z Q
+    const int nch = P->plan.n_gram_chunks;
+    LP_HIP(local_iter(P, k, q.Zw_shared, 0));
+    LP_HIP(launch_aggregate(m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, s));
+    LP_HIP(launch_cross_gram(1, d, k, q.Z, dk, q.Y, dk, q.gram, s));
+    LP_HIP(launch_sym_eig(nch, k, q.gram, ritz_out, q.omat, s));
+    LP_HIP(launch_right_mult(1, d, k, q.Z, q.omat, 0, false, Z_out, nullptr, 0, s));
+  } else {
+    LP_HIP(hipMemcpyAsync(Z_out, q.Z, dk * 8, hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<int32_t> flags(m + 2, 0);
+  LP_HIP(hipMemcpyAsync(flags.data(), q.flags, (m + 2) * 4, hipMemcpyDeviceToHost, s));
+  LP_HIP(hipStreamSynchronize(s));
+  if ((st = join_out(P)) != LP_OK) return st;
+  int breakdowns = 0;
+  for (int i = 0; i < m + 1; ++i) breakdowns += flags[i];
+  if (stats != nullptr) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, P->ev_t0, P->ev_t1);
+    stats->rounds = rounds;
+    stats->local_iters = iters;
+    stats->breakdowns = breakdowns;
+    stats->near_singular = flags[m + 1];
+    stats->ms_total = ms;
+    stats->bytes_A = (double)iters * (double)P->n * (double)P->d * (double)elem_bytes(P->dtype);
+    stats->ms_local = P->ms_local;
+    stats->local_launches = P->local_launches;
+    stats->reserved = 0;
+  }
+  if (breakdowns) return fail(LP_EBREAKDOWN, "Cholesky breakdown in an orthonormalisation");
+  return LP_OK;
+}
+
+lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y_out) {
+  if (P == nullptr || Z == nullptr || Y_out == nullptr) return fail(LP_EINVAL, "NULL argument");
+  lp_status st = check_k(P, k);
+  if (st != LP_OK) return st;
+  Ptrs q = ptrs(P);
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(launch_to_working(P->plan, 1, P->d, k, Z, q.Zw_shared, P->stream));
+  LP_HIP(launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
+                               P->stream));
+  LP_HIP(launch_reduce_partials(P->plan, k, q.part, q.slot_off, Y_out, P->stream));
+  return join_out(P);
+}
+
+lp_status lp_orth(lp_problem* P, int32_t k, int32_t batch, const double* Y, double* Q,
+                  int32_t* flags) {
+  if (P == nullptr || Y == nullptr || Q == nullptr) return fail(LP_EINVAL, "NULL argument");
+  if (k < 1 || k > P->k_max) return fail(LP_EINVAL, "need 1 <= k <= k_max");
+  if (batch < 1 || batch > std::max(P->m, 1)) return fail(LP_EINVAL, "need 1 <= batch <= m");
+  lp_status st;
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(cholqr2(P->plan, P->ws, batch, P->d, k, Y, Q, nullptr, flags, P->stream));
+  return join_out(P);
+}
+
+lp_status lp_align(lp_problem* P, int32_t k, int32_t batch, lp_agg mode, const double* Zi,
+                   const double* Zb, void* out) {
+  if (P == nullptr || Zi == nullptr || Zb == nullptr || out == nullptr)
+    return fail(LP_EINVAL, "NULL argument");
+  if (k < 1 || k > P->k_max) return fail(LP_EINVAL, "need 1 <= k <= k_max");
+  if (batch < 1 || batch > std::max(P->m, 1)) return fail(LP_EINVAL, "need 1 <= batch <= m");
+  if (mode != LP_AGG_SIGN && mode != LP_AGG_OPT) return fail(LP_EINVAL, "mode must be SIGN or OPT");
+  Ptrs q = ptrs(P);
+  const int64_t dk = P->d * k;
+  lp_status st;
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(launch_cross_gram(batch, P->d, k, Zi, dk, Zb, 0, q.gram, P->stream));
+  if (mode == LP_AGG_SIGN)
+    LP_HIP(launch_sign_from_gram(batch, P->plan.n_gram_chunks, k, q.gram, (int8_t*)out, P->stream));
+  else
+    LP_HIP(launch_procrustes(batch, P->plan.n_gram_chunks, k, q.gram, (double*)out, nullptr,
+                             P->stream));
+  return join_out(P);
+}
+
+lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
+                       void* stream) {
+  if (Z == nullptr || U == nullptr || out_host == nullptr) return fail(LP_EINVAL, "NULL argument");
+  if (d < 1 || k < 1 || k > kMaxK || k > d) return fail(LP_EINVAL, "need 1 <= k <= min(d, 64)");
+  hipStream_t s = (hipStream_t)stream;
+  double* slot = nullptr;
+  LP_HIP(sin_slot_address(&slot));
+  LP_HIP(launch_sin_theta(d, k, Z, U, slot, nullptr, nullptr, s));
+  LP_HIP(hipMemcpyAsync(out_host, slot, sizeof(double), hipMemcpyDeviceToHost, s));
+  LP_HIP(hipStreamSynchronize(s));
+  return LP_OK;
+}
+
+}  // extern "C"

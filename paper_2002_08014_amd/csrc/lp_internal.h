@@ -1,0 +1,172 @@
+// Internal declarations of the LocalPower HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lp.h"
+
+namespace lp {
+
+constexpr int kMaxK = 64;        // largest iteration rank supported by the kernels
+constexpr int kGramRows = 256;   // rows of a d x k matrix per Gram partial
+constexpr int kBlock = 256;      // threads per workgroup for the small kernels
+
+// A contiguous row range of one partition processed by one workgroup of the
+// local-multiply kernel; `slot` indexes its FP32/FP64 partial d x k sum.
+struct WorkItem {
+  int32_t part;
+  int32_t slot;
+  int64_t row0;
+  int64_t rows;
+};
+
+// Which local-multiply implementation a problem uses.
+enum class LocalPath : int { TwoPass = 0, Mfma32 = 1 };
+
+struct Layout {
+  // byte offsets into the workspace
+  size_t Zi, Zw, Yi, tmp, Z, Zw_shared, Y, Uref, part, tbuf, gram, rinv, omat, sgn, flags, items,
+      slot_off, hist, ctr, scal, total;
+};
+
+constexpr int kHistCap = 1024;  // rounds of sin-theta history buffered on the device
+
+// Sizes that decide the workspace layout.
+struct Plan {
+  lp_dtype dtype;
+  int64_t n, d;
+  int32_t m, k_max;
+  int64_t chunk_rows;        // rows per work item (last one of a partition is shorter)
+  std::vector<WorkItem> items;
+  int32_t n_gram_chunks;     // ceil(d / kGramRows)
+  size_t acc_bytes;          // 8 for FP64 A, 4 otherwise
+  size_t zw_bytes;           // bytes per element of the working copy of Z
+  LocalPath path;
+  Layout L;
+};
+
+bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int32_t m,
+               int32_t k_max, Plan* plan, std::string* err);
+
+struct GraphKey {
+  int32_t k, p, mode, hist;
+  bool operator<(const GraphKey& o) const {
+    if (k != o.k) return k < o.k;
+    if (p != o.p) return p < o.p;
+    if (mode != o.mode) return mode < o.mode;
+    return hist < o.hist;
+  }
+};
+
+}  // namespace lp
+
+struct lp_problem {
+  int device;
+  hipStream_t user_stream;
+  hipStream_t stream;          // own non-blocking stream (capturable)
+  hipEvent_t ev_join_in, ev_join_out, ev_t0, ev_t1;
+  const void* A;
+  lp_dtype dtype;
+  int64_t n, d, lda;
+  int32_t m, k_max, base;
+  std::vector<int64_t> offsets;
+  char* ws;
+  size_t ws_bytes;
+  lp::Plan plan;
+  std::map<lp::GraphKey, hipGraphExec_t> graphs;
+  // event pairs bracketing local-multiply launches when timing is requested
+  std::vector<hipEvent_t> ev_pool;
+  int ev_used = 0;
+  bool timing = false;
+  double ms_local = 0.0;
+  int local_launches = 0;
+};
+
+namespace lp {
+
+// ---------------------------------------------------------------------------
+// kernel launchers (all enqueue on `s`, return the launch status)
+// ---------------------------------------------------------------------------
+
+// Local multiply Y_i = A_i^T (A_i Z_i) for every work item, partial sums per item.
+//   Zw: working copy of the per-partition inputs, z_stride elements between
+//   partitions (0 = one shared Z).  Writes part[slot] (d x k, acc type).
+hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int k,
+                                 const void* Zw, int64_t z_stride, void* tbuf, void* part,
+                                 const WorkItem* items_dev, hipStream_t s);
+
+hipError_t launch_local_multiply_twopass(const Plan& P, const void* A, int64_t lda, int k,
+                                         const void* Zw, int64_t z_stride, void* tbuf, void* part,
+                                         const WorkItem* items, hipStream_t s);
+
+// Y_i = sum of the partials of partition i in item order (FP64); slot_off is
+// the device int32[m+1] prefix of partial slots per partition.
+hipError_t launch_reduce_partials(const Plan& P, int k, const void* part, const int32_t* slot_off,
+                                  double* Yi, hipStream_t s);
+
+// Convert FP64 d x k matrices to the working copy (FP32 or FP64), batch of them,
+// optionally scaling column j by sign[b*k+j] (int8, may be NULL).
+hipError_t launch_to_working(const Plan& P, int batch, int64_t d, int k, const double* X,
+                             void* Zw, hipStream_t s);
+
+// G_b = X_b^T W_b (k x k) partials over row chunks of kGramRows rows:
+//   X: batch x d x k; W: batch x d x k, or shared (w_stride = 0).
+hipError_t launch_cross_gram(int batch, int64_t d, int k, const double* X, int64_t x_stride,
+                             const double* W, int64_t w_stride, double* gram_part,
+                             hipStream_t s);
+
+// R_b^{-1} (upper triangular, k x k) from the Cholesky factor of
+// G_b = sum of the gram partials; flags[b] = 1 on breakdown.
+hipError_t launch_chol_inv(int batch, int nchunks, int k, const double* gram_part,
+                           double* rinv, int32_t* flags, hipStream_t s);
+
+// Q_b = X_b S_b (d x k times k x k); S upper triangular if `upper`.
+//   S stride k*k between batches (s_stride = 0: shared).  Optionally also writes
+//   the working copy of Q_b (zw != NULL, zw_bytes per element).
+hipError_t launch_right_mult(int batch, int64_t d, int k, const double* X, const double* S,
+                             int64_t s_stride, bool upper, double* Q, void* zw, size_t zw_bytes,
+                             hipStream_t s);
+
+// Sign decisions from the cross-Gram diagonals: sgn[b*k+j] = sign(sum of partials).
+hipError_t launch_sign_from_gram(int batch, int nchunks, int k, const double* gram_part,
+                                 int8_t* sgn, hipStream_t s);
+
+// Scale columns of X_b by sgn (in place), rewriting the working copy.
+hipError_t launch_apply_signs(int batch, int64_t d, int k, double* X, const int8_t* sgn,
+                              void* zw, size_t zw_bytes, hipStream_t s);
+
+// Procrustes factor O_b = W1 W2^T of C_b = sum of cross-gram partials (one-sided Jacobi).
+hipError_t launch_procrustes(int batch, int nchunks, int k, const double* gram_part,
+                             double* O, int32_t* flags, hipStream_t s);
+
+// Y = scale * sum_i Yi (fixed order), d x k.
+hipError_t launch_aggregate(int m, int64_t d, int k, const double* Yi, double scale, double* Y,
+                            hipStream_t s);
+
+// Symmetric k x k eigen-decomposition of H = sum of partials (cyclic Jacobi),
+// eigenvalues descending into lam, eigenvectors into V (k x k, columns).
+hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* lam, double* V,
+                          hipStream_t s);
+
+// sin theta_k in one workgroup (no scratch): writes out[0] (device) and, if
+// hist != NULL, hist[*ctr] then increments *ctr.
+hipError_t launch_sin_theta(int64_t d, int k, const double* Z, const double* U, double* out,
+                            double* hist, int32_t* ctr, hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
+
+// Address of the library's one-double device result slot used by lp_sin_theta.
+hipError_t sin_slot_address(double** p);
+
+// CholeskyQR2: Q_b = orth(Y_b) for a batch of d x k FP64 matrices, using
+// gram/rinv scratch from the plan; also writes the working copy when zw != NULL.
+hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
+                   double* Q, void* zw, int32_t* flags, hipStream_t s);
+
+}  // namespace lp

@@ -120,8 +120,10 @@ def lowrank_plus_noise(n: int, d: int, sigma: np.ndarray, noise: float, seed: in
 
     Draw order from one generator seeded with `seed`: V (d x d Gaussian, then
     Haar), U (n x d Gaussian, then Haar), then G in blocks of GEN_BLOCK_ROWS rows.
-    The product is formed in float64 and rounded once to `dtype`.
+    The product is formed in float64 and rounded once to `dtype`.  Needs n >= d.
     """
+    if n < d:
+        raise ValueError("low-rank-plus-noise needs n >= d (U is n x d orthonormal)")
     gen = _gen(seed, device)
     V = haar(d, d, gen, device)
     U = haar(n, d, gen, device)

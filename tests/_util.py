@@ -1,0 +1,36 @@
+"""Comparison helpers shared by the parity tests (no method arithmetic)."""
+
+import numpy as np
+import torch
+
+
+def host(x) -> np.ndarray:
+    if isinstance(x, torch.Tensor):
+        return x.detach().to("cpu", torch.float64).numpy() if x.dtype != torch.int8 else x.cpu().numpy()
+    return np.asarray(x)
+
+
+def sign_normalise(Z: np.ndarray) -> np.ndarray:
+    """Flip columns so that each column's largest-magnitude entry is positive."""
+    idx = np.argmax(np.abs(Z), axis=0)
+    s = np.sign(Z[idx, np.arange(Z.shape[1])])
+    s[s == 0] = 1.0
+    return Z * s
+
+
+def sin_theta_np(Z: np.ndarray, U: np.ndarray) -> float:
+    W = U - Z @ (Z.T @ U)
+    return float(np.linalg.norm(W, 2))
+
+
+def to_device(w, dtype=None):
+    """Move a workload's A to cuda:0 (optionally changing the stored dtype)."""
+    A = w.A
+    if dtype is not None:
+        A = A.to(dtype)
+    return A.to("cuda:0").contiguous()
+
+
+def upcast(A_dev: torch.Tensor) -> np.ndarray:
+    """Exact FP64 copy of the stored values (FP32/BF16 -> FP64 is exact)."""
+    return A_dev.to("cpu").to(torch.float64).numpy()

@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 A 1e-10 on Z and sin theta; FP32 (and BF16-stored, FP32
+accumulated) A 1e-5 on sin theta(Z_gpu, Z_oracle), the oracle running in FP64
+on the same stored values; integer outputs (sign decisions) bit-exact.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._util import host, sign_normalise, sin_theta_np, to_device, upcast
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _problem(lib, A_dev, offsets, k_max):
+    return lib.lp_create(A_dev, offsets, k_max)
+
+
+@pytest.fixture(scope="module")
+def lib(gpu_lib):
+    import paper_2002_08014_amd as lp
+    return lp
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = synth.make_c1()
+    A = w.A.numpy()
+    U, lam = oracle.top_k(A, w.k)
+    return w, A, U, lam
+
+
+# --------------------------------------------------------------------- C1 (FP64)
+
+@pytest.mark.parametrize("mode", ["sign", "opt", "vanilla"])
+def test_c1_full_run(lib, c1, mode):
+    w, A, U, lam = c1
+    _flush(f"c1 mode={mode}")
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    r = lib.lp_run(P, w.k, w.p_sched, mode, w.Y0, U_ref=torch.as_tensor(U), record_signs=True)
+    ro = oracle.localpower(A, w.offsets, w.k, w.p_sched, mode, w.Y0, U_ref=U)
+    Zg = host(r["Z"])
+    assert np.abs(Zg - ro["Z"]).max() < 1e-10
+    assert sin_theta_np(Zg, ro["Z"]) < 1e-10
+    assert np.abs(r["sin_hist"] - np.array(ro["sin_hist"])).max() < 1e-10
+    if mode == "sign":
+        assert ro["ambiguous"] == 0
+        exp = np.stack([s for s in ro["signs"]])
+        assert np.array_equal(r["signs"], exp)
+    st = r["stats"]
+    assert st["rounds"] == 30 and st["local_iters"] == 120 and st["breakdowns"] == 0
+
+
+def test_c1_p1_is_dpi(lib, c1):
+    w, A, U, lam = c1
+    _flush("c1 p=1")
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    r = lib.lp_run(P, w.k, [1] * 30, "sign", w.Y0)
+    Zd, _ = oracle.dpi(A, w.Y0, 30)
+    assert np.abs(host(r["Z"]) - Zd).max() < 1e-10
+    assert sin_theta_np(host(r["Z"]), U) < 1e-12
+
+
+def test_c1_decay_and_ritz(lib, c1):
+    w, A, U, lam = c1
+    _flush("c1 decay+ritz")
+    sched = synth.decay_schedule((8, 4, 2, 1), 10)
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    r = lib.lp_run(P, w.k, sched, "opt", w.Y0, ritz=True)
+    ro = oracle.localpower(A, w.offsets, w.k, sched, "opt", w.Y0)
+    lam_o, Zr_o, _ = oracle.ritz(A, ro["Z"])
+    rz = host(r["ritz"])
+    assert np.abs(rz - lam_o).max() < 1e-10 * lam_o[0]
+    assert np.abs(rz - lam[:w.k]).max() < 1e-9 * lam[0]
+    Zg = sign_normalise(host(r["Z"]))
+    assert np.abs(Zg - sign_normalise(Zr_o)).max() < 1e-8
+    assert sin_theta_np(Zg, U) < 1e-10
+
+
+def test_uneven_partitions_fp64(lib):
+    w = synth.make_small(3001, 77, 6, 5, seed=4, uneven=True, p_sched=[3] * 12)
+    _flush("uneven fp64")
+    A = w.A.numpy()
+    assert len(set(np.diff(w.offsets))) > 1
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    for mode in ("sign", "opt"):
+        r = lib.lp_run(P, w.k, w.p_sched, mode, w.Y0, record_signs=True)
+        ro = oracle.localpower(A, w.offsets, w.k, w.p_sched, mode, w.Y0)
+        assert np.abs(host(r["Z"]) - ro["Z"]).max() < 1e-10
+        if mode == "sign":
+            assert np.array_equal(r["signs"], np.stack(ro["signs"]))
+
+
+# --------------------------------------------------------------------- kernel-level
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("k", [1, 5, 16, 33])
+def test_local_multiply(lib, dtype, k):
+    """Y_i = A_i^T (A_i Z) for every partition; ragged rows/columns, uneven partitions."""
+    _flush(f"local multiply {dtype} k={k}")
+    n, d, m = 5000, 301, 4
+    w = synth.make_small(n, d, min(k, 8), m, seed=7, uneven=True)
+    A_dev = to_device(w, dtype)
+    A = upcast(A_dev)
+    P = _problem(lib, A_dev, w.offsets, k)
+    Z = oracle.orth(np.random.default_rng(1).standard_normal((d, k)))
+    Y = host(lib.lp_local_multiply(P, k, torch.as_tensor(Z)))
+    Zw = Z if dtype == torch.float64 else Z.astype(np.float32).astype(np.float64)
+    u = 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24
+    for i in range(m):
+        Ai = A[w.offsets[i]:w.offsets[i + 1]]
+        ref = Ai.T @ (Ai @ Zw)
+        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+        gamma = (d + Ai.shape[0]) * u
+        assert np.all(np.abs(Y[i] - ref) <= gamma * bound + 1e-300), (i, np.abs(Y[i] - ref).max())
+
+
+def test_orth_batched(lib):
+    _flush("orth")
+    rng = np.random.default_rng(3)
+    d, k, b = 333, 9, 3
+    w = synth.make_small(400, d, 4, 4, seed=1)
+    P = _problem(lib, to_device(w), w.offsets, k)
+    Y = rng.standard_normal((b, d, k)) @ np.diag(np.logspace(0, -4, k))
+    Q, flags = lib.lp_orth(P, torch.as_tensor(Y, device="cuda:0"))
+    Q = host(Q)
+    assert int(flags.sum()) == 0
+    for i in range(b):
+        assert np.abs(Q[i] - oracle.orth(Y[i])).max() < 1e-12
+        assert np.abs(Q[i].T @ Q[i] - np.eye(k)).max() < 1e-14
+
+
+def test_orth_breakdown_flag(lib):
+    """A rank-deficient iterate is reported (host-forced: a zero column)."""
+    _flush("orth breakdown")
+    w = synth.make_small(200, 50, 4, 4, seed=1)
+    P = _problem(lib, to_device(w), w.offsets, 4)
+    Y = np.random.default_rng(0).standard_normal((1, 50, 4))
+    Y[0, :, 2] = 0.0
+    _, flags = lib.lp_orth(P, torch.as_tensor(Y, device="cuda:0"))
+    assert int(flags[0]) == 1
+
+
+def test_align(lib):
+    _flush("align")
+    rng = np.random.default_rng(8)
+    d, k, b = 257, 12, 5
+    w = synth.make_small(400, d, 4, 5, seed=1)
+    P = _problem(lib, to_device(w), w.offsets, k)
+    Zb = oracle.orth(rng.standard_normal((d, k)))
+    Zi = np.stack([oracle.orth(Zb @ oracle.orth(rng.standard_normal((k, k))) * 1.0
+                               + 0.05 * rng.standard_normal((d, k))) for _ in range(b)])
+    sg = host(lib.lp_align(P, "sign", torch.as_tensor(Zi, device="cuda:0"),
+                           torch.as_tensor(Zb, device="cuda:0")))
+    O = host(lib.lp_align(P, "opt", torch.as_tensor(Zi, device="cuda:0"),
+                          torch.as_tensor(Zb, device="cuda:0")))
+    for i in range(b):
+        assert np.array_equal(sg[i], oracle.sign_fix(Zi[i], Zb).astype(np.int8))
+        assert np.abs(O[i] - oracle.opt_matrix(Zi[i], Zb)).max() < 1e-12
+
+
+def test_sin_theta(lib):
+    _flush("sin theta")
+    rng = np.random.default_rng(2)
+    for d, k in ((100, 5), (1024, 16), (4096, 64)):
+        U = oracle.orth(rng.standard_normal((d, k)))
+        Z = oracle.orth(U + 1e-3 * rng.standard_normal((d, k)))
+        g = lib.lp_sin_theta(torch.as_tensor(Z, device="cuda:0"), torch.as_tensor(U, device="cuda:0"))
+        o = oracle.sin_theta(Z, U)
+        assert abs(g - o) < 1e-12 * max(1.0, o) + 1e-6 * o
+
+
+# --------------------------------------------------------------------- FP32 / BF16 runs
+
+@pytest.mark.parametrize("mode", ["sign", "opt"])
+def test_fp32_run_parity(lib, mode):
+    _flush(f"fp32 run {mode}")
+    w = synth.make_small(32768, 256, 16, 8, seed=12, dtype=torch.float32, gap=1.3,
+                         p_sched=[4] * 20)
+    A_dev = to_device(w)
+    A = upcast(A_dev)
+    U, _ = oracle.top_k(A, 16)
+    P = _problem(lib, A_dev, w.offsets, 16)
+    r = lib.lp_run(P, 16, w.p_sched, mode, w.Y0, record_signs=(mode == "sign"))
+    ro = oracle.localpower(A, w.offsets, 16, w.p_sched, mode, w.Y0)
+    Zg = host(r["Z"])
+    assert sin_theta_np(Zg, ro["Z"]) < 1e-5
+    assert abs(sin_theta_np(Zg, U) - sin_theta_np(ro["Z"], U)) < 1e-5
+    if mode == "sign":
+        assert ro["ambiguous"] == 0
+        assert np.array_equal(r["signs"], np.stack(ro["signs"]))
+
+
+def test_bf16_run_parity(lib):
+    _flush("bf16 run")
+    w = synth.make_small(32768, 256, 16, 8, seed=13, dtype=torch.bfloat16, gap=1.3,
+                         p_sched=synth.decay_schedule((4, 2, 1), 6))
+    A_dev = to_device(w)
+    A = upcast(A_dev)
+    P = _problem(lib, A_dev, w.offsets, 16)
+    r = lib.lp_run(P, 16, w.p_sched, "opt", w.Y0)
+    ro = oracle.localpower(A, w.offsets, 16, w.p_sched, "opt", w.Y0)
+    assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
+
+
+# --------------------------------------------------------------------- runtime properties
+
+def test_graph_plain_and_repeat_bitwise(lib, c1):
+    w, A, U, lam = c1
+    _flush("graph vs plain")
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    r1 = lib.lp_run(P, w.k, w.p_sched, "opt", w.Y0, use_graph=True)
+    r2 = lib.lp_run(P, w.k, w.p_sched, "opt", w.Y0, use_graph=False)
+    r3 = lib.lp_run(P, w.k, w.p_sched, "opt", w.Y0, use_graph=True)
+    assert torch.equal(r1["Z"], r2["Z"]) and torch.equal(r1["Z"], r3["Z"])
+
+
+def test_resume_bitwise(lib, c1):
+    """State at a round boundary is Z alone: resuming from the saved Z gives the
+    uninterrupted result bit for bit."""
+    w, A, U, lam = c1
+    _flush("resume")
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    full = lib.lp_run(P, w.k, [4] * 12, "sign", w.Y0)
+    half = lib.lp_run(P, w.k, [4] * 5, "sign", w.Y0)
+    rest = lib.lp_run(P, w.k, [4] * 7, "sign", half["Z"], z0_orthonormal=True)
+    assert torch.equal(full["Z"], rest["Z"])
+
+
+def test_invalid_arguments(lib, c1):
+    w, A, U, lam = c1
+    _flush("invalid args")
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    with pytest.raises(lib.LPError):
+        lib.lp_run(P, w.k + 1, [4], "sign", w.Y0)            # k > k_max
+    with pytest.raises(lib.LPError):
+        lib.lp_run(P, w.k, [4, 0], "sign", w.Y0)             # p = 0
+    P2 = lib.lp_create(to_device(w), [0, 3, 2000], 5)
+    with pytest.raises(lib.LPError):
+        lib.lp_run(P2, 5, [1], "sign", w.Y0)                 # s_0 = 3 < k
+    with pytest.raises(lib.LPError):
+        lib.lp_create(to_device(w), [0, 3, 3, 2000], 5)      # empty partition
