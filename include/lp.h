@@ -89,6 +89,30 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
 
 lp_status lp_destroy(lp_problem* P);
 
+/* Tuning of the local-multiply kernel (what the autotuner varies).
+ *   local_kernel: 0 automatic; 1 generic two-pass kernel; 2..6 fused matrix-core kernel:
+ *                 2 four waves, two workgroups per CU; 3 four waves, one workgroup per CU;
+ *                 4 as 3 with two tiles in flight; 5 eight waves, one workgroup per CU;
+ *                 6 eight waves, two workgroups per CU; 7 software-pipelined (two LDS
+ *                 tiles, product 2 of one tile interleaved with product 1 of the next),
+ *                 eight waves; 8 pipelined with four waves (the eight-wave forms need
+ *                 d in {512, 1024}, else they run with four waves).  Fused variants need FP32 A, k = 16, d in
+ *                 {256, 512, 768, 1024}; other runs use the two-pass kernel.
+ *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
+ *                 default chosen at lp_create, which sized the workspace); 0 = default. */
+typedef struct {
+  int32_t struct_size;
+  int32_t local_kernel;
+  int64_t chunk_rows;
+} lp_tuning;
+
+/* Apply a tuning to a problem (host-side; re-uploads the work list on the problem's
+ * stream and drops captured graphs).  LP_EINVAL for values outside the ranges above. */
+lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t);
+
+/* Read the tuning in effect (local_kernel reports the variant actually used for k = 16). */
+lp_status lp_get_tuning(lp_problem* P, lp_tuning* t);
+
 /* Options of lp_run; zero-initialise and set struct_size = sizeof(lp_run_opts). */
 typedef struct {
   int32_t struct_size;
@@ -158,6 +182,12 @@ lp_status lp_orth(lp_problem* P, int32_t k, int32_t batch, const double* Y, doub
  * Same workspace/stream rules as lp_orth. */
 lp_status lp_align(lp_problem* P, int32_t k, int32_t batch, lp_agg mode, const double* Zi,
                    const double* Zb, void* out);
+
+/* Measured HBM read bandwidth: reads `bytes` (a multiple of 16, >= 16) of the device
+ * buffer `buf` once per launch, `iters` launches on `stream`, each bracketed by HIP
+ * events; writes the best launch's GB/s to *gbs_out.  Synchronous. */
+lp_status lp_bandwidth_probe(const void* buf, size_t bytes, int32_t iters, double* gbs_out,
+                             void* stream);
 
 /* sin theta_k(Z, U) = ||U - Z (Z^T U)||_2 (Definition 1), for device d x k FP64
  * matrices with orthonormal columns.  Uses its own small scratch on the stream

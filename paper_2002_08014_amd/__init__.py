@@ -11,9 +11,12 @@ from ._lib import (  # noqa: F401
     lp_workspace_size,
     lp_create,
     lp_destroy,
+    lp_set_tuning,
+    lp_get_tuning,
     lp_run,
     lp_local_multiply,
     lp_orth,
     lp_align,
     lp_sin_theta,
+    lp_bandwidth_probe,
 )

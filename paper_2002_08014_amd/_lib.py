@@ -23,13 +23,20 @@ DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
 MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
-           "lp_run", "lp_local_multiply", "lp_orth", "lp_align", "lp_sin_theta")
+           "lp_set_tuning", "lp_get_tuning", "lp_run", "lp_local_multiply", "lp_orth", "lp_align",
+           "lp_sin_theta", "lp_bandwidth_probe")
 
 
 class LPError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status}: {detail}")
         self.status = status
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32),
+                ("local_kernel", ctypes.c_int32),
+                ("chunk_rows", ctypes.c_int64)]
 
 
 class RunOpts(ctypes.Structure):
@@ -76,6 +83,10 @@ def load() -> ctypes.CDLL:
     L.lp_create.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i64, i64, vp, i32, i32, vp, sz, vp]
     L.lp_destroy.restype = i32
     L.lp_destroy.argtypes = [vp]
+    L.lp_set_tuning.restype = i32
+    L.lp_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.lp_get_tuning.restype = i32
+    L.lp_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lp_run.restype = i32
     L.lp_run.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(RunOpts),
                          ctypes.POINTER(RunStats)]
@@ -85,6 +96,8 @@ def load() -> ctypes.CDLL:
     L.lp_orth.argtypes = [vp, i32, i32, vp, vp, vp]
     L.lp_align.restype = i32
     L.lp_align.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+    L.lp_bandwidth_probe.restype = i32
+    L.lp_bandwidth_probe.argtypes = [vp, sz, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_sin_theta.restype = i32
     L.lp_sin_theta.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
     _LIB = L
@@ -182,6 +195,17 @@ def lp_destroy(P: Problem) -> None:
         P.handle = None
 
 
+def lp_set_tuning(P: Problem, local_kernel: int = 0, chunk_rows: int = 0) -> None:
+    t = Tuning(ctypes.sizeof(Tuning), local_kernel, chunk_rows)
+    _check(load().lp_set_tuning(P.handle, ctypes.byref(t)), "lp_set_tuning")
+
+
+def lp_get_tuning(P: Problem) -> dict:
+    t = Tuning()
+    _check(load().lp_get_tuning(P.handle, ctypes.byref(t)), "lp_get_tuning")
+    return {"local_kernel": t.local_kernel, "chunk_rows": t.chunk_rows}
+
+
 def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool = False,
            U_ref: Optional[torch.Tensor] = None, record_signs: bool = False,
            z0_orthonormal: bool = False, use_graph: bool = True, time_local: bool = False):
@@ -257,4 +281,15 @@ def lp_sin_theta(Z: torch.Tensor, U: torch.Tensor, stream: Optional[torch.cuda.S
     out = ctypes.c_double(0.0)
     _check(L.lp_sin_theta(_ptr(Zd), _ptr(Ud), Zd.shape[0], Zd.shape[1], ctypes.byref(out),
                           _stream_handle(stream)), "lp_sin_theta")
+    return float(out.value)
+
+
+def lp_bandwidth_probe(buf: torch.Tensor, iters: int = 5,
+                       stream: Optional[torch.cuda.Stream] = None) -> float:
+    """Best-of-`iters` read bandwidth (GB/s) over the bytes of a device tensor."""
+    L = load()
+    nbytes = (buf.numel() * buf.element_size()) // 16 * 16
+    out = ctypes.c_double(0.0)
+    _check(L.lp_bandwidth_probe(_ptr(buf), nbytes, iters, ctypes.byref(out), _stream_handle(stream)),
+           "lp_bandwidth_probe")
     return float(out.value)

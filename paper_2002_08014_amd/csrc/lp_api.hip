@@ -75,23 +75,14 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   P->acc_bytes = dtype == LP_F64 ? 8 : 4;
   P->zw_bytes = dtype == LP_F64 ? 8 : 4;
   P->path = LocalPath::TwoPass;
-  // about 1024 work items over the whole matrix, 64-row granularity
-  int64_t cr = (n + 1023) / 1024;
-  cr = ((cr + 63) / 64) * 64;
-  cr = std::max<int64_t>(64, std::min<int64_t>(cr, 4096));
-  P->chunk_rows = cr;
-  P->items.clear();
-  int32_t slot = 0;
-  for (int i = 0; i < m; ++i) {
-    for (int64_t r = offsets[i]; r < offsets[i + 1]; r += cr) {
-      WorkItem it;
-      it.part = i;
-      it.slot = slot++;
-      it.row0 = r;
-      it.rows = std::min<int64_t>(cr, offsets[i + 1] - r);
-      P->items.push_back(it);
-    }
-  }
+  P->lda = 0;
+  // about 512 work items (two resident workgroups per CU), 16-row granularity
+  int64_t cr = (n + 511) / 512;
+  cr = ((cr + 15) / 16) * 16;
+  cr = std::max<int64_t>(16, std::min<int64_t>(cr, 4096));
+  P->min_chunk_rows = cr;
+  P->variant = 0;
+  build_items(P, offsets, cr);
   P->n_gram_chunks = (int32_t)((d + kGramRows - 1) / kGramRows);
   const size_t dk = (size_t)d * k_max;
   const size_t mb = (size_t)std::max(m, 1);
@@ -126,9 +117,27 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   return true;
 }
 
+void build_items(Plan* P, const int64_t* offsets, int64_t cr) {
+  P->chunk_rows = cr;
+  P->items.clear();
+  int32_t slot = 0;
+  for (int i = 0; i < P->m; ++i) {
+    for (int64_t r = offsets[i]; r < offsets[i + 1]; r += cr) {
+      WorkItem it;
+      it.part = i;
+      it.slot = slot++;
+      it.row0 = r;
+      it.rows = std::min<int64_t>(cr, offsets[i + 1] - r);
+      P->items.push_back(it);
+    }
+  }
+}
+
 hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
                                  int64_t z_stride, void* tbuf, void* part,
                                  const WorkItem* items_dev, hipStream_t s) {
+  if (P.path == LocalPath::Mfma32 && mfma32_eligible(P.dtype, P.d, lda, k))
+    return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, s);
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
 }
 
@@ -313,6 +322,21 @@ lp_status join_out(lp_problem* P) {
   return LP_OK;
 }
 
+// Copy the work list and the per-partition slot prefix to the device (synchronous).
+lp_status upload_items(lp_problem* P) {
+  const int m = P->m;
+  std::vector<int32_t> slot_off(m + 1, 0);
+  for (const WorkItem& it : P->plan.items) slot_off[it.part + 1]++;
+  for (int i = 0; i < m; ++i) slot_off[i + 1] += slot_off[i];
+  Ptrs p = ptrs(P);
+  LP_HIP(hipMemcpyAsync(p.items, P->plan.items.data(), P->plan.items.size() * sizeof(WorkItem),
+                        hipMemcpyHostToDevice, P->stream));
+  LP_HIP(hipMemcpyAsync(p.slot_off, slot_off.data(), (m + 1) * sizeof(int32_t),
+                        hipMemcpyHostToDevice, P->stream));
+  LP_HIP(hipStreamSynchronize(P->stream));
+  return LP_OK;
+}
+
 lp_status check_k(lp_problem* P, int32_t k) {
   if (k < 1 || k > P->k_max) return fail(LP_EINVAL, "need 1 <= k <= k_max");
   for (int i = 0; i < P->m; ++i)
@@ -372,6 +396,8 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
     delete P;
     return fail(LP_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
   }
+  P->plan.lda = lda;
+  if (mfma32_eligible(dtype, d, lda, 16) && k_max >= 16) P->plan.path = LocalPath::Mfma32;
   P->A = A;
   P->dtype = dtype;
   P->n = n;
@@ -396,20 +422,15 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
     delete P;
     return fail(LP_EDEVICE, std::string("stream/event creation: ") + hipGetErrorString(e));
   }
-  // upload the work list and the slot prefix (synchronous, once)
-  std::vector<int32_t> slot_off(m + 1, 0);
-  for (const WorkItem& it : P->plan.items) slot_off[it.part + 1]++;
-  for (int i = 0; i < m; ++i) slot_off[i + 1] += slot_off[i];
-  Ptrs p = ptrs(P);
-  e = hipMemcpyAsync(p.items, P->plan.items.data(), P->plan.items.size() * sizeof(WorkItem),
-                     hipMemcpyHostToDevice, P->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p.slot_off, slot_off.data(), (m + 1) * sizeof(int32_t),
-                       hipMemcpyHostToDevice, P->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-  if (e != hipSuccess) {
+  // The workspace belongs to the caller's stream: wait for it before the first
+  // write, since its memory may have been handed back while kernels queued on
+  // that stream still use it.
+  lp_status ust = join_in(P);
+  if (ust == LP_OK) ust = upload_items(P);
+  if (ust != LP_OK) {
+    std::string msg = g_err;
     lp_destroy(P);
-    return fail(LP_EDEVICE, std::string("upload of the work list: ") + hipGetErrorString(e));
+    return fail(ust, "upload of the work list: " + msg);
   }
   *out = P;
   return LP_OK;
@@ -429,6 +450,37 @@ lp_status lp_destroy(lp_problem* P) {
   if (P->ev_t0) (void)hipEventDestroy(P->ev_t0);
   if (P->ev_t1) (void)hipEventDestroy(P->ev_t1);
   delete P;
+  return LP_OK;
+}
+
+lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
+  if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
+    return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
+  if (t->local_kernel < 0 || t->local_kernel > 8) return fail(LP_EINVAL, "local_kernel out of range");
+  int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
+  if (cr % 16 != 0 || cr < P->plan.min_chunk_rows)
+    return fail(LP_EINVAL, "chunk_rows must be a multiple of 16 and >= the default");
+  lp_status jst = join_in(P);
+  if (jst != LP_OK) return jst;
+  LP_HIP(hipStreamSynchronize(P->stream));
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  P->graphs.clear();
+  const bool fused_ok = mfma32_eligible(P->dtype, P->d, P->lda, 16) && P->k_max >= 16;
+  if (t->local_kernel == 1 || (t->local_kernel >= 2 && !fused_ok)) {
+    P->plan.path = LocalPath::TwoPass;
+  } else if (fused_ok) {
+    P->plan.path = LocalPath::Mfma32;
+    P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 0;
+  }
+  build_items(&P->plan, P->offsets.data(), cr);
+  return upload_items(P);
+}
+
+lp_status lp_get_tuning(lp_problem* P, lp_tuning* t) {
+  if (P == nullptr || t == nullptr) return fail(LP_EINVAL, "NULL argument");
+  t->struct_size = sizeof(lp_tuning);
+  t->local_kernel = P->plan.path == LocalPath::TwoPass ? 1 : 2 + P->plan.variant;
+  t->chunk_rows = P->plan.chunk_rows;
   return LP_OK;
 }
 
@@ -586,6 +638,33 @@ lp_status lp_align(lp_problem* P, int32_t k, int32_t batch, lp_agg mode, const d
     LP_HIP(launch_procrustes(batch, P->plan.n_gram_chunks, k, q.gram, (double*)out, nullptr,
                              P->stream));
   return join_out(P);
+}
+
+lp_status lp_bandwidth_probe(const void* buf, size_t bytes, int32_t iters, double* gbs_out,
+                             void* stream) {
+  if (buf == nullptr || gbs_out == nullptr || bytes < 16 || (bytes % 16) != 0 || iters < 1 ||
+      ((uintptr_t)buf & 15) != 0)
+    return fail(LP_EINVAL, "need a 16-byte aligned buffer, bytes a multiple of 16, iters >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  LP_HIP(hipEventCreate(&e0));
+  LP_HIP(hipEventCreate(&e1));
+  double best = 0.0;
+  hipError_t err = hipSuccess;
+  for (int it = 0; it < iters && err == hipSuccess; ++it) {
+    err = hipEventRecord(e0, s);
+    if (err == hipSuccess) err = launch_stream_read(buf, bytes, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms > 0.f) best = std::max(best, (double)bytes / (ms * 1e-3) / 1e9);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(LP_EDEVICE, std::string("bandwidth probe: ") + hipGetErrorString(err));
+  *gbs_out = best;
+  return LP_OK;
 }
 
 lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,

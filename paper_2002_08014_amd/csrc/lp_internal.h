@@ -42,14 +42,20 @@ struct Plan {
   lp_dtype dtype;
   int64_t n, d;
   int32_t m, k_max;
+  int64_t lda;               // leading dimension of A (set by lp_create; 0 before)
   int64_t chunk_rows;        // rows per work item (last one of a partition is shorter)
   std::vector<WorkItem> items;
   int32_t n_gram_chunks;     // ceil(d / kGramRows)
   size_t acc_bytes;          // 8 for FP64 A, 4 otherwise
   size_t zw_bytes;           // bytes per element of the working copy of Z
   LocalPath path;
+  int32_t variant;           // fused kernel variant: 0 two WGs/CU, 1 one WG/CU, 2 one WG/CU + 2 tiles ahead
+  int64_t min_chunk_rows;    // the default chunking the workspace was sized for
   Layout L;
 };
+
+// Rebuild the work list for `chunk_rows` rows per item (>= plan.min_chunk_rows).
+void build_items(Plan* P, const int64_t* offsets, int64_t chunk_rows);
 
 bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int32_t m,
                int32_t k_max, Plan* plan, std::string* err);
@@ -100,6 +106,12 @@ namespace lp {
 hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int k,
                                  const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                  const WorkItem* items_dev, hipStream_t s);
+
+// Fused single-pass matrix-core kernel: FP32 A, k = 16, d in {256, 512, 768, 1024}.
+bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k);
+hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t lda, int k,
+                                        const void* Zw, int64_t z_stride, void* part,
+                                        const WorkItem* items, hipStream_t s);
 
 hipError_t launch_local_multiply_twopass(const Plan& P, const void* A, int64_t lda, int k,
                                          const void* Zw, int64_t z_stride, void* tbuf, void* part,
@@ -160,6 +172,9 @@ hipError_t launch_sin_theta(int64_t d, int k, const double* Z, const double* U, 
                             double* hist, int32_t* ctr, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
+
+// Read `bytes` (a multiple of 16) of `buf` once with 128-bit loads.
+hipError_t launch_stream_read(const void* buf, size_t bytes, hipStream_t s);
 
 // Address of the library's one-double device result slot used by lp_sin_theta.
 hipError_t sin_slot_address(double** p);

@@ -1,0 +1,101 @@
+"""Parity of the fused matrix-core local multiply (FP32 A, k = 16) against the
+FP64 oracle, for every kernel variant, at small shapes with ragged tiles and at
+the full 262144 x 1024 benchmark shape (sampled partitions)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._util import host, sin_theta_np, upcast
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = (1, 2, 3, 4, 5, 6, 7, 8)   # two-pass, then the fused forms (see lp_tuning)
+
+
+@pytest.fixture(scope="module")
+def lp(gpu_lib):
+    import paper_2002_08014_amd as lp
+    return lp
+
+
+def _check_partitions(Y, A, offsets, Zw, parts):
+    u = 2.0 ** -24
+    for i in parts:
+        Ai = A[offsets[i]:offsets[i + 1]]
+        ref = Ai.T @ (Ai @ Zw)
+        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+        gamma = (Ai.shape[1] + Ai.shape[0]) * u
+        err = np.abs(Y[i] - ref)
+        assert np.all(err <= gamma * bound), (i, float(err.max()), float((gamma * bound).min()))
+
+
+@pytest.mark.parametrize("d", [256, 512, 768, 1024])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_fused_small(lp, d, variant):
+    print(f"fused small d={d} variant={variant}", flush=True)
+    n, m = 3 * d + 37, 3
+    w = synth.make_small(n, d, 16, m, seed=d, dtype=torch.float32, uneven=True)
+    A_dev = w.A.to("cuda:0")
+    A = upcast(A_dev)
+    P = lp.lp_create(A_dev, w.offsets, 16)
+    lp.lp_set_tuning(P, variant, 0)
+    t = lp.lp_get_tuning(P)
+    assert t["local_kernel"] == variant
+    Z = oracle.orth(np.random.default_rng(d).standard_normal((d, 16)))
+    Y = host(lp.lp_local_multiply(P, 16, torch.as_tensor(Z)))
+    _check_partitions(Y, A, w.offsets, Z.astype(np.float32).astype(np.float64), range(m))
+
+
+def test_fused_other_k_falls_back(lp):
+    """k != 16 on a fused-eligible problem runs the generic kernel, still exact."""
+    w = synth.make_small(2048, 256, 8, 2, seed=1, dtype=torch.float32)
+    A_dev = w.A.to("cuda:0")
+    P = lp.lp_create(A_dev, w.offsets, 16)
+    Z = oracle.orth(np.random.default_rng(2).standard_normal((256, 8)))
+    Y = host(lp.lp_local_multiply(P, 8, torch.as_tensor(Z)))
+    _check_partitions(Y, upcast(A_dev), w.offsets, Z.astype(np.float32).astype(np.float64), range(2))
+
+
+@pytest.fixture(scope="module")
+def c2(lp):
+    print("generating the 262144 x 1024 FP32 workload", flush=True)
+    w = synth.make_c2(device="cuda:0", rounds=3)
+    return w
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_fused_full_size_sampled(lp, c2, variant):
+    """Bench shape, the launch configuration the benchmark times: sampled partitions."""
+    print(f"full-size local multiply variant={variant}", flush=True)
+    w = c2
+    P = lp.lp_create(w.A, w.offsets, 16)
+    lp.lp_set_tuning(P, variant, 0)
+    Z = oracle.orth(np.random.default_rng(5).standard_normal((w.d, 16)))
+    Y = host(lp.lp_local_multiply(P, 16, torch.as_tensor(Z)))
+    parts = (0, 13, 31)
+    A = {}
+    for i in parts:
+        A[i] = w.A[w.offsets[i]:w.offsets[i + 1]].to("cpu").to(torch.float64).numpy()
+    Zw = Z.astype(np.float32).astype(np.float64)
+    u = 2.0 ** -24
+    for i in parts:
+        ref = A[i].T @ (A[i] @ Zw)
+        bound = np.abs(A[i]).T @ (np.abs(A[i]) @ np.abs(Zw))
+        assert np.all(np.abs(Y[i] - ref) <= (w.d + A[i].shape[0]) * u * bound)
+
+
+def test_full_size_run_parity(lp, c2):
+    """Three rounds of p = 4 sign-fixing at the bench shape against the oracle on
+    the same FP32 values: subspace within 1e-5, sign decisions bit-exact."""
+    print("full-size run vs oracle", flush=True)
+    w = c2
+    P = lp.lp_create(w.A, w.offsets, 16)
+    r = lp.lp_run(P, 16, w.p_sched, "sign", w.Y0, record_signs=True)
+    A = w.A.to("cpu").to(torch.float64).numpy()
+    ro = oracle.localpower(A, w.offsets, 16, w.p_sched, "sign", w.Y0)
+    assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
+    assert ro["ambiguous"] == 0
+    assert np.array_equal(r["signs"], np.stack(ro["signs"]))

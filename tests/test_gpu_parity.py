@@ -250,3 +250,21 @@ def test_invalid_arguments(lib, c1):
         lib.lp_run(P2, 5, [1], "sign", w.Y0)                 # s_0 = 3 < k
     with pytest.raises(lib.LPError):
         lib.lp_create(to_device(w), [0, 3, 3, 2000], 5)      # empty partition
+
+
+def test_create_right_after_queued_work(lib):
+    """Regression: the workspace may reuse memory that kernels still queued on
+    the caller's stream write; lp_create and lp_set_tuning must wait for that
+    stream before their first write to it."""
+    _flush("create after queued work")
+    w = synth.make_small(20000, 256, 16, 8, seed=21, dtype=torch.float32, p_sched=[4] * 4)
+    A_dev = w.A.to("cuda:0")
+    for _ in range(3):
+        x = torch.randn(4096, 4096, device="cuda:0")
+        y = x @ x
+        del x, y
+        P = lib.lp_create(A_dev, w.offsets, 16)
+        lib.lp_set_tuning(P, 0, 0)
+        r = lib.lp_run(P, 16, w.p_sched, "sign", w.Y0)
+    ro = oracle.localpower(upcast(A_dev), w.offsets, 16, w.p_sched, "sign", w.Y0)
+    assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
