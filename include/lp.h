@@ -90,20 +90,24 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
 lp_status lp_destroy(lp_problem* P);
 
 /* Tuning of the local-multiply kernel (what the autotuner varies).
- *   local_kernel: 0 automatic; 1 generic two-pass kernel; 2..6 fused matrix-core kernel:
- *                 2 four waves, two workgroups per CU; 3 four waves, one workgroup per CU;
- *                 4 as 3 with two tiles in flight; 5 eight waves, one workgroup per CU;
- *                 6 eight waves, two workgroups per CU; 7 software-pipelined (two LDS
- *                 tiles, product 2 of one tile interleaved with product 1 of the next),
- *                 eight waves; 8 pipelined with four waves (the eight-wave forms need
- *                 d in {512, 1024}, else they run with four waves).  Fused variants need FP32 A, k = 16, d in
- *                 {256, 512, 768, 1024}; other runs use the two-pass kernel.
+ *   local_kernel: 0 automatic; 1 generic two-pass kernel; 2..5 fused matrix-core kernel
+ *                 with one workgroup per CU: 2 four waves; 3 eight waves; 4 software-
+ *                 pipelined (two LDS tiles, product 2 of one tile interleaved with
+ *                 product 1 of the next), eight waves; 5 pipelined, four waves; 6 eight
+ *                 waves with the next two tiles in flight (deeper prefetch).  The
+ *                 eight-wave forms need d in {512, 1024} (else they run with four waves).
+ *                 Fused variants need FP32 A, k = 16, d in {256, 512, 768, 1024}; other
+ *                 runs use the two-pass kernel.
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
- *                 default chosen at lp_create, which sized the workspace); 0 = default. */
+ *                 default chosen at lp_create, which sized the workspace); 0 = default.
+ *   cached_loads: 1 reads A with ordinary (cached) loads in the fused kernel; 0 (default)
+ *                 with nontemporal loads, since A is streamed once per local iteration. */
 typedef struct {
   int32_t struct_size;
   int32_t local_kernel;
   int64_t chunk_rows;
+  int32_t cached_loads;
+  int32_t reserved;
 } lp_tuning;
 
 /* Apply a tuning to a problem (host-side; re-uploads the work list on the problem's
@@ -112,6 +116,15 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t);
 
 /* Read the tuning in effect (local_kernel reports the variant actually used for k = 16). */
 lp_status lp_get_tuning(lp_problem* P, lp_tuning* t);
+
+/* Pick the fastest local-multiply tuning for rank k on this problem and apply it.
+ * Times every candidate (kernel variant x work-item size x load flavour) with HIP events
+ * around a few launches on the problem's stream (A is only read; the workspace's working
+ * copy of Z is overwritten with zeros).  cache_path: text file of earlier choices keyed by
+ * device architecture, dtype, n, d, m, k and lda (read first, appended to); NULL uses the
+ * environment variable LP_AUTOTUNE_CACHE, and no cache when that is unset.  Writes the
+ * chosen tuning to *chosen (may be NULL).  Synchronous. */
+lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tuning* chosen);
 
 /* Options of lp_run; zero-initialise and set struct_size = sizeof(lp_run_opts). */
 typedef struct {
@@ -125,8 +138,9 @@ typedef struct {
   int32_t use_graph;    /* 1 (default when struct_size covers it and it is 1): replay each
                            round shape as a captured hipGraph; 0: plain launches */
   int32_t time_local;   /* 1: bracket every local-multiply launch with a pair of HIP events
-                           on the problem's stream and report their summed duration in
-                           stats->ms_local (forces plain launches) */
+                           on the problem's stream (captured as event nodes when rounds are
+                           replayed as graphs) and report their summed duration in
+                           stats->ms_local */
 } lp_run_opts;
 
 typedef struct {
@@ -139,7 +153,7 @@ typedef struct {
   double ms_local;         /* with opts->time_local: summed duration of the local-multiply
                               launches (HIP events), else 0 */
   int32_t local_launches;  /* local-multiply launches timed into ms_local */
-  int32_t reserved;
+  int32_t graph_rounds;    /* rounds replayed from captured hipGraphs */
 } lp_run_stats;
 
 /* Run LocalPower (Algorithm 1) for T communication rounds.
@@ -188,6 +202,13 @@ lp_status lp_align(lp_problem* P, int32_t k, int32_t batch, lp_agg mode, const d
  * events; writes the best launch's GB/s to *gbs_out.  Synchronous. */
 lp_status lp_bandwidth_probe(const void* buf, size_t bytes, int32_t iters, double* gbs_out,
                              void* stream);
+
+/* Measured HBM copy bandwidth: copies `bytes` (a multiple of 16) from device `src` to
+ * device `dst` (non-overlapping, 16-byte aligned) once per launch, `iters` launches on
+ * `stream`; writes the best launch's GB/s, counting read plus written bytes (2 * bytes),
+ * to *gbs_out.  Synchronous.  Also the known-traffic kernel for calibrating counters. */
+lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters, double* gbs_out,
+                        void* stream);
 
 /* sin theta_k(Z, U) = ||U - Z (Z^T U)||_2 (Definition 1), for device d x k FP64
  * matrices with orthonormal columns.  Uses its own small scratch on the stream

@@ -13,10 +13,12 @@ from ._lib import (  # noqa: F401
     lp_destroy,
     lp_set_tuning,
     lp_get_tuning,
+    lp_autotune,
     lp_run,
     lp_local_multiply,
     lp_orth,
     lp_align,
     lp_sin_theta,
     lp_bandwidth_probe,
+    lp_copy_probe,
 )

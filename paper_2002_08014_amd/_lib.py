@@ -23,8 +23,8 @@ DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
 MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
-           "lp_set_tuning", "lp_get_tuning", "lp_run", "lp_local_multiply", "lp_orth", "lp_align",
-           "lp_sin_theta", "lp_bandwidth_probe")
+           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_local_multiply", "lp_orth", "lp_align",
+           "lp_sin_theta", "lp_bandwidth_probe", "lp_copy_probe")
 
 
 class LPError(RuntimeError):
@@ -36,7 +36,9 @@ class LPError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32),
                 ("local_kernel", ctypes.c_int32),
-                ("chunk_rows", ctypes.c_int64)]
+                ("chunk_rows", ctypes.c_int64),
+                ("cached_loads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RunOpts(ctypes.Structure):
@@ -58,7 +60,7 @@ class RunStats(ctypes.Structure):
                 ("bytes_A", ctypes.c_double),
                 ("ms_local", ctypes.c_double),
                 ("local_launches", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("graph_rounds", ctypes.c_int32)]
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -87,6 +89,8 @@ def load() -> ctypes.CDLL:
     L.lp_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lp_get_tuning.restype = i32
     L.lp_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.lp_autotune.restype = i32
+    L.lp_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     L.lp_run.restype = i32
     L.lp_run.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(RunOpts),
                          ctypes.POINTER(RunStats)]
@@ -98,6 +102,8 @@ def load() -> ctypes.CDLL:
     L.lp_align.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     L.lp_bandwidth_probe.restype = i32
     L.lp_bandwidth_probe.argtypes = [vp, sz, i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.lp_copy_probe.restype = i32
+    L.lp_copy_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_sin_theta.restype = i32
     L.lp_sin_theta.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
     _LIB = L
@@ -195,15 +201,26 @@ def lp_destroy(P: Problem) -> None:
         P.handle = None
 
 
-def lp_set_tuning(P: Problem, local_kernel: int = 0, chunk_rows: int = 0) -> None:
-    t = Tuning(ctypes.sizeof(Tuning), local_kernel, chunk_rows)
+def lp_set_tuning(P: Problem, local_kernel: int = 0, chunk_rows: int = 0,
+                  cached_loads: bool = False) -> None:
+    t = Tuning(ctypes.sizeof(Tuning), local_kernel, chunk_rows, 1 if cached_loads else 0, 0)
     _check(load().lp_set_tuning(P.handle, ctypes.byref(t)), "lp_set_tuning")
 
 
 def lp_get_tuning(P: Problem) -> dict:
     t = Tuning()
     _check(load().lp_get_tuning(P.handle, ctypes.byref(t)), "lp_get_tuning")
-    return {"local_kernel": t.local_kernel, "chunk_rows": t.chunk_rows}
+    return {"local_kernel": t.local_kernel, "chunk_rows": t.chunk_rows,
+            "cached_loads": bool(t.cached_loads)}
+
+
+def lp_autotune(P: Problem, k: int, cache_path: Optional[str] = None) -> dict:
+    """Time the local-multiply candidates for rank k, apply the fastest, return it."""
+    t = Tuning()
+    _check(load().lp_autotune(P.handle, k, cache_path.encode() if cache_path else None,
+                              ctypes.byref(t)), "lp_autotune")
+    return {"local_kernel": t.local_kernel, "chunk_rows": t.chunk_rows,
+            "cached_loads": bool(t.cached_loads)}
 
 
 def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool = False,
@@ -292,4 +309,15 @@ def lp_bandwidth_probe(buf: torch.Tensor, iters: int = 5,
     out = ctypes.c_double(0.0)
     _check(L.lp_bandwidth_probe(_ptr(buf), nbytes, iters, ctypes.byref(out), _stream_handle(stream)),
            "lp_bandwidth_probe")
+    return float(out.value)
+
+
+def lp_copy_probe(dst: torch.Tensor, src: torch.Tensor, iters: int = 5,
+                  stream: Optional[torch.cuda.Stream] = None) -> float:
+    """Best-of-`iters` copy bandwidth (GB/s, read + written bytes) from src to dst."""
+    L = load()
+    nbytes = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
+    out = ctypes.c_double(0.0)
+    _check(L.lp_copy_probe(_ptr(dst), _ptr(src), nbytes, iters, ctypes.byref(out),
+                           _stream_handle(stream)), "lp_copy_probe")
     return float(out.value)

@@ -107,9 +107,16 @@ __global__ void reduce_partials_kernel(int64_t dk, const TC* __restrict__ part,
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= dk) return;
   const int s0 = slot_off[i], s1 = slot_off[i + 1];
-  double s = 0.0;
-  for (int sl = s0; sl < s1; ++sl) s += (double)part[(int64_t)sl * dk + e];
-  Yi[(int64_t)i * dk + e] = s;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int sl = s0;
+  for (; sl + 3 < s1; sl += 4) {
+    a0 += (double)part[(int64_t)sl * dk + e];
+    a1 += (double)part[(int64_t)(sl + 1) * dk + e];
+    a2 += (double)part[(int64_t)(sl + 2) * dk + e];
+    a3 += (double)part[(int64_t)(sl + 3) * dk + e];
+  }
+  for (; sl < s1; ++sl) a0 += (double)part[(int64_t)sl * dk + e];
+  Yi[(int64_t)i * dk + e] = (a0 + a1) + (a2 + a3);
 }
 
 template <typename TA, typename TC, int KB>

@@ -28,8 +28,17 @@ constexpr int kTileRows = 16;
 
 __device__ inline int swz(int c4) { return c4 ^ ((c4 >> 4) & 3); }
 
+// 128-bit load of A; nontemporal when A is streamed without reuse.
+template <bool NT>
+__device__ inline f4 ldA(const float* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load((const f4*)p);
+  else
+    return *(const f4*)p;
+}
+
 // NQ: 16-column groups per wave slice; W: waves per workgroup (d = 16*NQ*W).
-template <int NQ, int W, int OCC, int PF>
+template <int NQ, int W, int OCC, int PF, bool NTL>
 __global__ void __launch_bounds__(64 * W, OCC)
 k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
@@ -72,7 +81,7 @@ k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restric
       const int e = j * NT + tid;
       const int r = e / CPR, c4 = e % CPR;
       if (r0 + r < rows)
-        pre[j] = *(const f4*)(Ab + (int64_t)(r0 + r) * lda + 4 * c4);
+        pre[j] = ldA<NTL>(Ab + (int64_t)(r0 + r) * lda + 4 * c4);
       else
         pre[j] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -89,22 +98,24 @@ k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restric
     __syncthreads();
     if (r0 + PF * kTileRows < rows) load_tile(pre, r0 + PF * kTileRows);
 
+    // all LDS operands of both products first, so the waits count down
+    f4 a1[NQ], a2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a1[q] = *(const f4*)&tile[i * P + 4 * swz(c4s + 4 * q + g)];
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+      a2[st] = *(const f4*)&tile[(4 * g + s) * P + 4 * swz(c4s + (NQ / 4) * i + cq)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the whole read batch ahead of the MFMAs
     // product 1: partial t over this wave's slice (two independent chains)
     f4 tw0 = f4{0.f, 0.f, 0.f, 0.f}, tw1 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const f4 a = *(const f4*)&tile[i * P + 4 * swz(c4s + 4 * q + g)];
-      if (q & 1) {
-        tw1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], zr[q][0], tw1, 0, 0, 0);
-        tw1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], zr[q][1], tw1, 0, 0, 0);
-        tw1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], zr[q][2], tw1, 0, 0, 0);
-        tw1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], zr[q][3], tw1, 0, 0, 0);
-      } else {
-        tw0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], zr[q][0], tw0, 0, 0, 0);
-        tw0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], zr[q][1], tw0, 0, 0, 0);
-        tw0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], zr[q][2], tw0, 0, 0, 0);
-        tw0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], zr[q][3], tw0, 0, 0, 0);
-      }
+      f4& tw = (q & 1) ? tw1 : tw0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q][c], zr[q][c], tw, 0, 0, 0);
     }
     tpart[w][lane] = tw0 + tw1;
     __syncthreads();
@@ -114,16 +125,11 @@ k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restric
 
     // product 2: Y_slice += A_tile^T t
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float* trow = &tile[(4 * g + s) * P];
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
 #pragma unroll
-      for (int cq = 0; cq < NQ / 4; ++cq) {
-        const f4 a = *(const f4*)&trow[4 * swz(c4s + (NQ / 4) * i + cq)];
-        acc[4 * cq + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], t[s], acc[4 * cq + 0], 0, 0, 0);
-        acc[4 * cq + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], t[s], acc[4 * cq + 1], 0, 0, 0);
-        acc[4 * cq + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], t[s], acc[4 * cq + 2], 0, 0, 0);
-        acc[4 * cq + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], t[s], acc[4 * cq + 3], 0, 0, 0);
-      }
+      for (int c = 0; c < 4; ++c)
+        acc[4 * cq + c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[st][c], t[s], acc[4 * cq + c], 0, 0, 0);
     }
     __syncthreads();
   };
@@ -152,7 +158,7 @@ k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restric
 // Software-pipelined form: two LDS tile buffers; in each step, product 2 of
 // tile t and product 1 of tile t+1 are interleaved (independent matrix-core
 // work from two tiles), with two barriers per tile.  One workgroup per CU.
-template <int NQ, int W>
+template <int NQ, int W, bool NTL>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
                      int64_t z_stride, const WorkItem* __restrict__ items,
@@ -196,7 +202,7 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
       const int e = j * NT + tid;
       const int r = e / CPR, c4 = e % CPR;
       if (r0 + r < rows)
-        pre[j] = *(const f4*)(Ab + (int64_t)(r0 + r) * lda + 4 * c4);
+        pre[j] = ldA<NTL>(Ab + (int64_t)(r0 + r) * lda + 4 * c4);
       else
         pre[j] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -209,20 +215,26 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
       *(f4*)&tile[b][r * P + 4 * swz(c4)] = pre[j];
     }
   };
-  auto p1_step = [&](const float* tb, int q, f4& tw) {
-    const f4 a = *(const f4*)&tb[i * P + 4 * swz(c4s + 4 * q + g)];
-    tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], zr[q][0], tw, 0, 0, 0);
-    tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], zr[q][1], tw, 0, 0, 0);
-    tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], zr[q][2], tw, 0, 0, 0);
-    tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], zr[q][3], tw, 0, 0, 0);
+  auto rd1 = [&](const float* tb, f4 (&a)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = *(const f4*)&tb[i * P + 4 * swz(c4s + 4 * q + g)];
   };
-  auto p2_step = [&](const float* tb, int st, const f4& t) {
+  auto rd2 = [&](const float* tb, f4 (&a)[NQ]) {
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+      a[st] = *(const f4*)&tb[(4 * g + s) * P + 4 * swz(c4s + (NQ / 4) * i + cq)];
+    }
+  };
+  auto p1 = [&](const f4 (&a)[NQ], int q, f4& tw) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][c], zr[q][c], tw, 0, 0, 0);
+  };
+  auto p2 = [&](const f4 (&a)[NQ], int st, const f4& t) {
     const int s = st / (NQ / 4), cq = st % (NQ / 4);
-    const f4 a = *(const f4*)&tb[(4 * g + s) * P + 4 * swz(c4s + (NQ / 4) * i + cq)];
-    acc[4 * cq + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], t[s], acc[4 * cq + 0], 0, 0, 0);
-    acc[4 * cq + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], t[s], acc[4 * cq + 1], 0, 0, 0);
-    acc[4 * cq + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], t[s], acc[4 * cq + 2], 0, 0, 0);
-    acc[4 * cq + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], t[s], acc[4 * cq + 3], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      acc[4 * cq + c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st][c], t[s], acc[4 * cq + c], 0, 0, 0);
   };
 
   // prologue: tiles 0 and 1 staged, tile 2 in registers, product 1 of tile 0
@@ -235,29 +247,35 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
   if (ntiles > 2) load_tile(2);
   __syncthreads();
   {
+    f4 a1[NQ];
+    rd1(tile[0], a1);
     f4 tw0 = f4{0.f, 0.f, 0.f, 0.f}, tw1 = tw0;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) p1_step(tile[0], q, (q & 1) ? tw1 : tw0);
+    for (int q = 0; q < NQ; ++q) p1(a1, q, (q & 1) ? tw1 : tw0);
     tpart[0][w][lane] = tw0 + tw1;
   }
   for (int t = 0; t < ntiles; ++t) {
     __syncthreads();
+    const float* cur = tile[t & 1];
+    f4 a2[NQ];
+    rd2(cur, a2);
     f4 tt = tpart[t & 1][0][lane];
 #pragma unroll
     for (int v = 1; v < W; ++v) tt += tpart[t & 1][v][lane];
-    const float* cur = tile[t & 1];
     if (t + 1 < ntiles) {
-      const float* nxt = tile[(t + 1) & 1];
+      f4 a1[NQ];
+      rd1(tile[(t + 1) & 1], a1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the whole read batch ahead of the MFMAs
       f4 tw0 = f4{0.f, 0.f, 0.f, 0.f}, tw1 = tw0;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        p1_step(nxt, q, (q & 1) ? tw1 : tw0);
-        p2_step(cur, q, tt);
+        p2(a2, q, tt);
+        p1(a1, q, (q & 1) ? tw1 : tw0);
       }
       tpart[(t + 1) & 1][w][lane] = tw0 + tw1;
     } else {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) p2_step(cur, q, tt);
+      for (int q = 0; q < NQ; ++q) p2(a2, q, tt);
     }
     __syncthreads();
     if (t + 2 < ntiles) {
@@ -272,25 +290,25 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
     for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
 }
 
-template <int NQ, int W>
+template <int NQ, int W, bool NT>
 hipError_t launch_pipe_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
                           const WorkItem* items, float* o, hipStream_t s) {
   if constexpr (16 * NQ * W <= 1024) {
-    k1_mfma_f32_k16_pipe<NQ, W><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_f32_k16_pipe<NQ, W, NT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-template <int W>
+template <int W, bool NT>
 hipError_t launch_f32_pipe(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
                            int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
   switch (d / (16 * W)) {
-    case 4: return launch_pipe_nq<4, W>(nitems, a, lda, z, z_stride, items, o, s);
-    case 8: return launch_pipe_nq<8, W>(nitems, a, lda, z, z_stride, items, o, s);
-    case 12: return launch_pipe_nq<12, W>(nitems, a, lda, z, z_stride, items, o, s);
-    case 16: return launch_pipe_nq<16, W>(nitems, a, lda, z, z_stride, items, o, s);
+    case 4: return launch_pipe_nq<4, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 8: return launch_pipe_nq<8, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 12: return launch_pipe_nq<12, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 16: return launch_pipe_nq<16, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -298,18 +316,27 @@ hipError_t launch_f32_pipe(int64_t d, int nitems, const float* a, int64_t lda, c
 }  // namespace
 
 
-template <int W, int OCC, int PF>
+template <int NQ, int W, int OCC, int PF, bool NT>
+hipError_t launch_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
+                     const WorkItem* items, float* o, hipStream_t s) {
+  if constexpr (16 * NQ * W <= 1024) {
+    k1_mfma_f32_k16<NQ, W, OCC, PF, NT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int W, int OCC, int PF, bool NT>
 hipError_t launch_f32(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
                       int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
-  constexpr int NT = 64 * W;
   switch (d / (16 * W)) {
-    case 4: k1_mfma_f32_k16<4, W, OCC, PF><<<nitems, NT, 0, s>>>(a, lda, z, z_stride, items, o); break;
-    case 8: k1_mfma_f32_k16<8, W, OCC, PF><<<nitems, NT, 0, s>>>(a, lda, z, z_stride, items, o); break;
-    case 12: k1_mfma_f32_k16<12, W, OCC, PF><<<nitems, NT, 0, s>>>(a, lda, z, z_stride, items, o); break;
-    case 16: k1_mfma_f32_k16<16, W, OCC, PF><<<nitems, NT, 0, s>>>(a, lda, z, z_stride, items, o); break;
+    case 4: return launch_nq<4, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 8: return launch_nq<8, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 12: return launch_nq<12, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 16: return launch_nq<16, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
@@ -317,9 +344,27 @@ bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
          (lda % 4) == 0;
 }
 
-// Variants: 0: 4 waves, 2 WG/CU; 1: 4 waves, 1 WG/CU; 2: 4 waves, 1 WG/CU, two tiles in
-// flight; 3: 8 waves, 1 WG/CU; 4: 8 waves, 2 WG/CU; 5: pipelined, 8 waves; 6: pipelined,
-// 4 waves.  The 8-wave forms need d in {512, 1024} (else they run with 4 waves).
+// Variants: 0: 4 waves, 1 WG/CU; 1: 8 waves, 1 WG/CU; 2: pipelined, 8 waves;
+// 3: pipelined, 4 waves; 4: 8 waves with two tiles in flight.  The 8-wave forms need d in {512, 1024} (else 4 waves).
+template <bool NT>
+hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, const float* z,
+                        int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+  const bool w8 = P.d == 512 || P.d == 1024;
+  switch (P.variant) {
+    case 1:
+      if (w8) return launch_f32<8, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    case 2:
+      if (w8) return launch_f32_pipe<8, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      return launch_f32_pipe<4, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    case 3: return launch_f32_pipe<4, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    case 4:
+      if (w8) return launch_f32<8, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      return launch_f32<4, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    default: return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+  }
+}
+
 hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
                                         const WorkItem* items, hipStream_t s) {
@@ -327,22 +372,8 @@ hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t ld
   const float* a = (const float*)A;
   const float* z = (const float*)Zw;
   float* o = (float*)part;
-  const bool w8 = P.d >= 512 && P.d != 768;
-  switch (P.variant) {
-    case 1: return launch_f32<4, 1, 1>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    case 2: return launch_f32<4, 1, 2>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    case 3:
-      if (w8) return launch_f32<8, 1, 1>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32<4, 1, 1>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    case 4:
-      if (w8) return launch_f32<8, 2, 1>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32<4, 1, 1>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    case 5:
-      if (w8) return launch_f32_pipe<8>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32_pipe<4>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    case 6: return launch_f32_pipe<4>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    default: return launch_f32<4, 2, 1>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-  }
+  if (P.nt_loads) return dispatch_f32<true>(P, nitems, a, lda, z, z_stride, items, o, s);
+  return dispatch_f32<false>(P, nitems, a, lda, z, z_stride, items, o, s);
 }
 
 }  // namespace lp

@@ -8,22 +8,45 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Each workgroup streams one contiguous chunk with eight 128-bit nontemporal
+// loads in flight per thread (the pattern that reaches the highest read rate).
 __global__ void __launch_bounds__(256) stream_read_kernel(const f4* __restrict__ p, int64_t n4,
                                                           float* __restrict__ sink) {
-  f4 acc0 = f4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; e + 3 * stride < n4; e += 4 * stride) {
-    acc0 += p[e];
-    acc1 += p[e + stride];
-    acc2 += p[e + 2 * stride];
-    acc3 += p[e + 3 * stride];
+  constexpr int U = 8;
+  const int64_t per = (n4 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < n4 ? b0 + per : n4;
+  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  int64_t e = b0 + threadIdx.x;
+  for (; e + (U - 1) * 256 < b1; e += U * 256) {
+    f4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(p + e + u * 256);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
   }
-  for (; e < n4; e += stride) acc0 += p[e];
-  const f4 a = acc0 + acc1 + acc2 + acc3;
-  const float v = a[0] + a[1] + a[2] + a[3];
+  for (; e < b1; e += 256) acc += __builtin_nontemporal_load(p + e);
+  const float v = acc[0] + acc[1] + acc[2] + acc[3];
   // keeps the loads alive; a sum of exactly this value essentially never occurs
   if (v == 1234.5678f) sink[blockIdx.x & 1023] = v;
+}
+
+// Copy with the same streaming pattern (known read and write traffic).
+__global__ void __launch_bounds__(256) stream_copy_kernel(f4* __restrict__ dst,
+                                                          const f4* __restrict__ src, int64_t n4) {
+  constexpr int U = 8;
+  const int64_t per = (n4 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < n4 ? b0 + per : n4;
+  int64_t e = b0 + threadIdx.x;
+  for (; e + (U - 1) * 256 < b1; e += U * 256) {
+    f4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + e + u * 256);
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[e + u * 256] = v[u];
+  }
+  for (; e < b1; e += 256) dst[e] = __builtin_nontemporal_load(src + e);
 }
 
 }  // namespace
@@ -35,7 +58,12 @@ hipError_t launch_stream_read(const void* buf, size_t bytes, hipStream_t s) {
   hipError_t e = hipGetSymbolAddress((void**)&sink, HIP_SYMBOL(g_probe_sink));
   if (e != hipSuccess) return e;
   const int64_t n4 = (int64_t)(bytes / 16);
-  stream_read_kernel<<<256 * 16, 256, 0, s>>>((const f4*)buf, n4, sink);
+  stream_read_kernel<<<2048, 256, 0, s>>>((const f4*)buf, n4, sink);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  stream_copy_kernel<<<2048, 256, 0, s>>>((f4*)dst, (const f4*)src, (int64_t)(bytes / 16));
   return hipGetLastError();
 }
 

@@ -59,16 +59,26 @@ cross_gram_kernel(int64_t d, int k, const double* __restrict__ X, int64_t x_stri
   }
 }
 
+// sum_{q < n} p[q * stride] with eight interleaved accumulators combined in a
+// fixed order (deterministic, and eight loads in flight instead of one).
+template <typename T>
+__device__ inline double sum_strided(const T* __restrict__ p, int64_t stride, int n) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 7 < n; q += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += (double)p[(int64_t)(q + u) * stride];
+  }
+  for (; q < n; ++q) a[q & 7] += (double)p[(int64_t)q * stride];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // Sum of the gram partials of batch b into an LDS k x k array (fixed order).
 __device__ void sum_partials(const double* __restrict__ part, int b, int nchunks, int k,
                              double* G) {
   const int kk = k * k;
-  for (int e = threadIdx.x; e < kk; e += blockDim.x) {
-    double s = 0.0;
-    const double* p = part + (int64_t)b * nchunks * kk + e;
-    for (int c = 0; c < nchunks; ++c) s += p[(int64_t)c * kk];
-    G[e] = s;
-  }
+  for (int e = threadIdx.x; e < kk; e += blockDim.x)
+    G[e] = sum_strided(part + (int64_t)b * nchunks * kk + e, kk, nchunks);
 }
 
 // ---------------------------------------------------------------------------
@@ -122,6 +132,296 @@ chol_inv_kernel(int nchunks, int k, const double* __restrict__ part, double* __r
     out[e] = v;
   }
   if (threadIdx.x == 0 && flags != nullptr && bad) flags[b] = 1;
+}
+
+
+
+__device__ inline double rdlane(double v, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky G = R^T R (upper R, positive diagonal) of the k x k LDS matrix G and
+// R^{-1} into the LDS matrix Ri, by the first wavefront of the block: lane c
+// holds column c in registers and rows are broadcast with readlane, so no block
+// barrier is needed inside.  On breakdown (non-positive or non-finite pivot)
+// *bad is set and Ri is the identity.  Call from all threads; returns after a
+// block barrier with Ri ready.
+template <int KM>
+__device__ void chol_inv_wave(const double* G, double* Ri, int k, int* bad) {
+  if (threadIdx.x < 64) {
+    const int c = threadIdx.x;
+    double g[KM], r[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) g[i] = (c < k && i < k) ? G[i * k + c] : 0.0;
+    bool badw = false;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (j < k) {
+        double djj = rdlane(g[j], j);
+        if (!(djj > 0.0) || !isfinite(djj)) {
+          badw = true;
+          djj = 1.0;
+        }
+        const double rjj = sqrt(djj);
+        const double rjc = (c == j) ? rjj : ((c > j && c < k) ? g[j] / rjj : 0.0);
+        r[j] = rjc;
+#pragma unroll
+        for (int i = j + 1; i < KM; ++i) {
+          if (i < k) {
+            const double rji = rdlane(rjc, i);
+            if (c >= i) g[i] -= rji * rjc;
+          }
+        }
+      } else {
+        r[j] = 0.0;
+      }
+    }
+    // back substitution R x = e_c; x overwrites g
+#pragma unroll
+    for (int i = KM - 1; i >= 0; --i) {
+      if (i < k) {
+        double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = i + 1; l < KM; ++l)
+          if (l < k) sacc -= rdlane(r[i], l) * g[l];
+        g[i] = sacc / rdlane(r[i], i);
+      } else {
+        g[i] = 0.0;
+      }
+    }
+    if (c < k) {
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (i < k) Ri[i * k + c] = badw ? (i == c ? 1.0 : 0.0) : g[i];
+    }
+    if (c == 0 && badw) *bad = 1;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of the k x k LDS matrix R (in place: upper R with R^T R = G, positive
+// diagonal) and the inverse of R into X.  All threads of the block take part.
+// *bad is set on breakdown (non-positive or non-finite pivot), and then R^{-1}
+// is replaced by the identity so that downstream values stay finite.
+// ---------------------------------------------------------------------------
+__device__ void chol_inv_block(double* R, double* X, int k, int* bad) {
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      double djj = R[j * k + j];
+      for (int l = 0; l < j; ++l) djj -= R[l * k + j] * R[l * k + j];
+      if (!(djj > 0.0) || !isfinite(djj)) {
+        *bad = 1;
+        djj = 1.0;
+      }
+      R[j * k + j] = sqrt(djj);
+    }
+    __syncthreads();
+    const double rjj = R[j * k + j];
+    for (int c = j + 1 + threadIdx.x; c < k; c += blockDim.x) {
+      double v = R[j * k + c];
+      for (int l = 0; l < j; ++l) v -= R[l * k + j] * R[l * k + c];
+      R[j * k + c] = v / rjj;
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    for (int i = c + 1; i < k; ++i) X[i * k + c] = 0.0;
+    X[c * k + c] = 1.0 / R[c * k + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1; l <= c; ++l) s += R[i * k + l] * X[l * k + c];
+      X[i * k + c] = -s / R[i * k + i];
+    }
+  }
+  __syncthreads();
+  if (*bad)
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) X[e] = (e / k == e % k) ? 1.0 : 0.0;
+  __syncthreads();
+}
+
+// Gram partial of the `rows` x k LDS block Qs into out[k*k] (k*k <= KM*KM).
+template <int KM>
+__device__ void gram_block(const double* Qs, int rows, int k, double* out) {
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e - (e / k) * k;
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r) s = fma(Qs[r * k + i], Qs[r * k + j], s);
+    out[e] = s;
+  }
+}
+
+// grid (nch, m): Y_i rows of chunk c = sum of the partition's partial slots, and their Gram.
+template <typename TC, int KM>
+__global__ void __launch_bounds__(kBlock)
+reduce_gram_kernel(int64_t d, int k, const TC* __restrict__ part,
+                   const int32_t* __restrict__ slot_off, double* __restrict__ Yi,
+                   double* __restrict__ gram) {
+  __shared__ double ys[kGramRows * KM];
+  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  const int64_t dk = d * k;
+  const int s0 = slot_off[b], s1 = slot_off[b + 1];
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
+    const double v = sum_strided(part + (int64_t)s0 * dk + r0 * k + e, dk, s1 - s0);
+    Yi[(int64_t)b * dk + r0 * k + e] = v;
+    ys[e] = v;
+  }
+  __syncthreads();
+  gram_block<KM>(ys, rows, k, gram + ((int64_t)b * nch + c) * k * k);
+}
+
+// grid (nch): Y rows = scale * sum_i Yi rows, and their Gram.
+template <int KM>
+__global__ void __launch_bounds__(kBlock)
+aggregate_gram_kernel(int m, int64_t d, int k, const double* __restrict__ Yi, double scale,
+                      double* __restrict__ Y, double* __restrict__ gram) {
+  __shared__ double ys[kGramRows * KM];
+  const int c = blockIdx.x;
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  const int64_t dk = d * k;
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
+    const double v = scale * sum_strided(Yi + r0 * k + e, dk, m);
+    Y[r0 * k + e] = v;
+    ys[e] = v;
+  }
+  __syncthreads();
+  gram_block<KM>(ys, rows, k, gram + (int64_t)c * k * k);
+}
+
+// grid (nch, batch): one CholeskyQR pass for row chunk c of matrix b.
+template <typename TW, int KM>
+__global__ void __launch_bounds__(kBlock)
+chol_apply_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ gin,
+                  double* __restrict__ Q, TW* __restrict__ zw, double* __restrict__ gout,
+                  int32_t* __restrict__ flags) {
+  __shared__ double R[KM * KM];
+  __shared__ double Ri[KM * KM];
+  __shared__ double qs[kGramRows * KM];
+  __shared__ int bad;
+  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
+  if (threadIdx.x == 0) bad = 0;
+  sum_partials(gin, b, nch, k, R);
+  __syncthreads();
+  chol_inv_wave<KM>(R, Ri, k, &bad);
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  const int64_t base = (int64_t)b * d * k + r0 * k;
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
+    const int rr = e / k, j = e - (e / k) * k;
+    const double* xr = X + base + (int64_t)rr * k;
+    double v = 0.0;
+    for (int l = 0; l <= j; ++l) v = fma(xr[l], Ri[l * k + j], v);
+    Q[base + e] = v;
+    if (zw != nullptr) zw[base + e] = (TW)v;
+    qs[e] = v;
+  }
+  if (gout != nullptr) {
+    __syncthreads();
+    gram_block<KM>(qs, rows, k, gout + ((int64_t)b * nch + c) * k * k);
+  }
+  if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
+}
+
+
+// grid (batch), block kBlock: R^{-1} of chol(sum of the Gram partials) for
+// matrix b (all threads sum the partials, the first wavefront factors).
+template <int KM>
+__global__ void __launch_bounds__(kBlock)
+chol_inv_wave_kernel(int nch, int k, const double* __restrict__ gin, double* __restrict__ rinv,
+                     int32_t* __restrict__ flags) {
+  __shared__ double G[KM * KM];
+  __shared__ double Ri[KM * KM];
+  __shared__ int bad;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) bad = 0;
+  sum_partials(gin, b, nch, k, G);
+  __syncthreads();
+  chol_inv_wave<KM>(G, Ri, k, &bad);
+  for (int e = threadIdx.x; e < k * k; e += kBlock) rinv[(int64_t)b * k * k + e] = Ri[e];
+  if (threadIdx.x == 0 && bad && flags != nullptr) flags[b] = 1;
+}
+
+// grid (nch, batch): Q = X R^{-1} for row chunk c of matrix b (R^{-1} upper, from rinv),
+// optional working copy and Gram partials of Q.
+template <typename TW, int KM>
+__global__ void __launch_bounds__(kBlock)
+apply_gram_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ rinv,
+                  double* __restrict__ Q, TW* __restrict__ zw, double* __restrict__ gout) {
+  __shared__ double Ri[KM * KM];
+  __shared__ double qs[kGramRows * KM];
+  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
+  for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rinv[(int64_t)b * k * k + e];
+  __syncthreads();
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  const int64_t base = (int64_t)b * d * k + r0 * k;
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
+    const int rr = e / k, j = e - (e / k) * k;
+    const double* xr = X + base + (int64_t)rr * k;
+    double v = 0.0;
+    for (int l = 0; l <= j; ++l) v = fma(xr[l], Ri[l * k + j], v);
+    Q[base + e] = v;
+    if (zw != nullptr) zw[base + e] = (TW)v;
+    qs[e] = v;
+  }
+  if (gout != nullptr) {
+    __syncthreads();
+    gram_block<KM>(qs, rows, k, gout + ((int64_t)b * nch + c) * k * k);
+  }
+}
+
+// grid (nch, batch): partial column dots of chunk c: part[(b*nch + c)*k + j].
+__global__ void __launch_bounds__(kBlock)
+diag_dot_kernel(int64_t d, int k, const double* __restrict__ Zi, const double* __restrict__ Zb,
+                double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  // thread t: column j = t % k, rows t / k, t / k + (kBlock / k), ...
+  const int per = kBlock / k;             // threads per column (k <= 64)
+  const int j = threadIdx.x % k, r = threadIdx.x / k;
+  double s = 0.0;
+  if (r < per)
+    for (int rr = r; rr < rows; rr += per)
+      s = fma(Zi[(int64_t)b * d * k + (r0 + rr) * k + j], Zb[(r0 + rr) * k + j], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double t = 0.0;
+    for (int q = 0; q < per; ++q) t += red[q * k + threadIdx.x];
+    part[((int64_t)b * nch + c) * k + threadIdx.x] = t;
+  }
+}
+
+// grid (nch, batch): sign of the summed dots, applied to chunk c of Zi (and zw).
+template <typename TW>
+__global__ void __launch_bounds__(kBlock)
+sign_apply_kernel(int64_t d, int k, const double* __restrict__ part, double* __restrict__ Zi,
+                  TW* __restrict__ zw, int8_t* __restrict__ sgn) {
+  __shared__ double sg[kMaxK];
+  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
+  if (threadIdx.x < k) {
+    double t = 0.0;
+    for (int q = 0; q < nch; ++q) t += part[((int64_t)b * nch + q) * k + threadIdx.x];
+    const double v = (t >= 0.0) ? 1.0 : -1.0;
+    sg[threadIdx.x] = v;
+    if (c == 0 && sgn != nullptr) sgn[b * k + threadIdx.x] = (v > 0.0) ? (int8_t)1 : (int8_t)-1;
+  }
+  __syncthreads();
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  const int64_t base = (int64_t)b * d * k + r0 * k;
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
+    const double v = Zi[base + e] * sg[e % k];
+    Zi[base + e] = v;
+    if (zw != nullptr) zw[base + e] = (TW)v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -584,6 +884,96 @@ hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* l
 hipError_t launch_sin_theta(int64_t d, int k, const double* Z, const double* U, double* out,
                             double* hist, int32_t* ctr, hipStream_t s) {
   sin_theta_kernel<<<1, kBlock, 0, s>>>(d, k, Z, U, out, hist, ctr);
+  return hipGetLastError();
+}
+
+
+
+hipError_t launch_reduce_gram(const Plan& P, int k, const void* part, const int32_t* slot_off,
+                              double* Yi, double* gram, hipStream_t s) {
+  dim3 grid(nblk(P.d, kGramRows), P.m);
+  if (P.acc_bytes == 8) {
+    if (k <= 16) reduce_gram_kernel<double, 16><<<grid, kBlock, 0, s>>>(P.d, k, (const double*)part, slot_off, Yi, gram);
+    else reduce_gram_kernel<double, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, (const double*)part, slot_off, Yi, gram);
+  } else {
+    if (k <= 16) reduce_gram_kernel<float, 16><<<grid, kBlock, 0, s>>>(P.d, k, (const float*)part, slot_off, Yi, gram);
+    else reduce_gram_kernel<float, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, (const float*)part, slot_off, Yi, gram);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_aggregate_gram(int m, int64_t d, int k, const double* Yi, double scale, double* Y,
+                                 double* gram, hipStream_t s) {
+  dim3 grid(nblk(d, kGramRows));
+  if (k <= 16) aggregate_gram_kernel<16><<<grid, kBlock, 0, s>>>(m, d, k, Yi, scale, Y, gram);
+  else aggregate_gram_kernel<kMaxK><<<grid, kBlock, 0, s>>>(m, d, k, Yi, scale, Y, gram);
+  return hipGetLastError();
+}
+
+template <typename TW>
+static void chol_apply_t(dim3 grid, int64_t d, int k, const double* X, const double* gin, double* Q,
+                         TW* zw, double* gout, int32_t* flags, hipStream_t s) {
+  if (k <= 16)
+    chol_apply_kernel<TW, 16><<<grid, kBlock, 0, s>>>(d, k, X, gin, Q, zw, gout, flags);
+  else if (k <= 32)
+    chol_apply_kernel<TW, 32><<<grid, kBlock, 0, s>>>(d, k, X, gin, Q, zw, gout, flags);
+  else
+    chol_apply_kernel<TW, kMaxK><<<grid, kBlock, 0, s>>>(d, k, X, gin, Q, zw, gout, flags);
+}
+
+hipError_t launch_chol_apply(int batch, int64_t d, int k, const double* X, const double* gram_in,
+                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
+                             int32_t* flags, hipStream_t s) {
+  dim3 grid(nblk(d, kGramRows), batch);
+  if (zw == nullptr || zw_bytes == 8)
+    chol_apply_t<double>(grid, d, k, X, gram_in, Q, (double*)zw, gram_out, flags, s);
+  else
+    chol_apply_t<float>(grid, d, k, X, gram_in, Q, (float*)zw, gram_out, flags, s);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_chol_inv_wave(int batch, int nch, int k, const double* gram, double* rinv,
+                                int32_t* flags, hipStream_t s) {
+  if (k <= 16) chol_inv_wave_kernel<16><<<batch, kBlock, 0, s>>>(nch, k, gram, rinv, flags);
+  else if (k <= 32) chol_inv_wave_kernel<32><<<batch, kBlock, 0, s>>>(nch, k, gram, rinv, flags);
+  else chol_inv_wave_kernel<kMaxK><<<batch, kBlock, 0, s>>>(nch, k, gram, rinv, flags);
+  return hipGetLastError();
+}
+
+template <typename TW>
+static void apply_gram_t(dim3 grid, int64_t d, int k, const double* X, const double* rinv,
+                         double* Q, TW* zw, double* gout, hipStream_t s) {
+  if (k <= 16) apply_gram_kernel<TW, 16><<<grid, kBlock, 0, s>>>(d, k, X, rinv, Q, zw, gout);
+  else if (k <= 32) apply_gram_kernel<TW, 32><<<grid, kBlock, 0, s>>>(d, k, X, rinv, Q, zw, gout);
+  else apply_gram_kernel<TW, kMaxK><<<grid, kBlock, 0, s>>>(d, k, X, rinv, Q, zw, gout);
+}
+
+hipError_t launch_apply_gram(int batch, int64_t d, int k, const double* X, const double* rinv,
+                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
+                             hipStream_t s) {
+  dim3 grid(nblk(d, kGramRows), batch);
+  if (zw == nullptr || zw_bytes == 8)
+    apply_gram_t<double>(grid, d, k, X, rinv, Q, (double*)zw, gram_out, s);
+  else
+    apply_gram_t<float>(grid, d, k, X, rinv, Q, (float*)zw, gram_out, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_dot(int batch, int64_t d, int k, const double* Zi, const double* Zb,
+                           double* part, hipStream_t s) {
+  dim3 grid(nblk(d, kGramRows), batch);
+  diag_dot_kernel<<<grid, kBlock, 0, s>>>(d, k, Zi, Zb, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sign_apply(int batch, int64_t d, int k, const double* part, double* Zi, void* zw,
+                             size_t zw_bytes, int8_t* sgn, hipStream_t s) {
+  dim3 grid(nblk(d, kGramRows), batch);
+  if (zw == nullptr || zw_bytes == 8)
+    sign_apply_kernel<double><<<grid, kBlock, 0, s>>>(d, k, part, Zi, (double*)zw, sgn);
+  else
+    sign_apply_kernel<float><<<grid, kBlock, 0, s>>>(d, k, part, Zi, (float*)zw, sgn);
   return hipGetLastError();
 }
 

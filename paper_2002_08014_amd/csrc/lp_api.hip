@@ -4,8 +4,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -81,7 +84,8 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   cr = ((cr + 15) / 16) * 16;
   cr = std::max<int64_t>(16, std::min<int64_t>(cr, 4096));
   P->min_chunk_rows = cr;
-  P->variant = 0;
+  P->variant = 1;
+  P->nt_loads = true;
   build_items(P, offsets, cr);
   P->n_gram_chunks = (int32_t)((d + kGramRows - 1) / kGramRows);
   const size_t dk = (size_t)d * k_max;
@@ -104,6 +108,7 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   L.part = take(P->items.size() * dk * P->acc_bytes);
   L.tbuf = take((size_t)n * k_max * P->acc_bytes);
   L.gram = take(mb * P->n_gram_chunks * (size_t)k_max * k_max * 8);
+  L.gram2 = take(mb * P->n_gram_chunks * (size_t)k_max * k_max * 8);
   L.rinv = take(mb * (size_t)k_max * k_max * 8);
   L.omat = take(mb * (size_t)k_max * k_max * 8);
   L.sgn = take(mb * k_max);
@@ -141,25 +146,30 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
 }
 
-hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y, double* Q,
-                   void* zw, int32_t* flags, hipStream_t s) {
+hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
+                             double* Q, void* zw, int32_t* flags, hipStream_t s) {
   const Layout& L = P.L;
   double* gram = (double*)(ws + L.gram);
+  double* gram2 = (double*)(ws + L.gram2);
   double* rinv = (double*)(ws + L.rinv);
   double* tmp = (double*)(ws + L.tmp);
   const int nch = (int)((d + kGramRows - 1) / kGramRows);
-  const int64_t dk = d * k;
   hipError_t e;
-  // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}
-  if ((e = launch_cross_gram(batch, d, k, Y, dk, Y, dk, gram, s)) != hipSuccess) return e;
-  if ((e = launch_chol_inv(batch, nch, k, gram, rinv, flags, s)) != hipSuccess) return e;
-  if ((e = launch_right_mult(batch, d, k, Y, rinv, (int64_t)k * k, true, tmp, nullptr, 0, s)) !=
-      hipSuccess)
+  // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}, and the Gram partials of Q1
+  if ((e = launch_chol_inv_wave(batch, nch, k, gram, rinv, flags, s)) != hipSuccess) return e;
+  if ((e = launch_apply_gram(batch, d, k, Y, rinv, tmp, nullptr, 0, gram2, s)) != hipSuccess)
     return e;
-  // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1}
-  if ((e = launch_cross_gram(batch, d, k, tmp, dk, tmp, dk, gram, s)) != hipSuccess) return e;
-  if ((e = launch_chol_inv(batch, nch, k, gram, rinv, flags, s)) != hipSuccess) return e;
-  return launch_right_mult(batch, d, k, tmp, rinv, (int64_t)k * k, true, Q, zw, P.zw_bytes, s);
+  // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1} (and the working copy)
+  if ((e = launch_chol_inv_wave(batch, nch, k, gram2, rinv, flags, s)) != hipSuccess) return e;
+  return launch_apply_gram(batch, d, k, tmp, rinv, Q, zw, P.zw_bytes, nullptr, s);
+}
+
+hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y, double* Q,
+                   void* zw, int32_t* flags, hipStream_t s) {
+  const int64_t dk = d * k;
+  hipError_t e = launch_cross_gram(batch, d, k, Y, dk, Y, dk, (double*)(ws + P.L.gram), s);
+  if (e != hipSuccess) return e;
+  return cholqr2_from_gram(P, ws, batch, d, k, Y, Q, zw, flags, s);
 }
 
 }  // namespace lp
@@ -218,23 +228,49 @@ hipError_t drain_timing(lp_problem* P) {
   return hipSuccess;
 }
 
-// One local iteration on every partition: Yi = A_i^T (A_i Z_i).
+// Add an event-record node to the graph being captured on `s`, after the nodes
+// the stream's next operation would depend on, and make it the new dependency.
+hipError_t capture_event_node(hipStream_t s, hipEvent_t ev) {
+  hipStreamCaptureStatus st;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  hipError_t e = hipStreamGetCaptureInfo_v2(s, &st, &id, &g, &deps, &nd);
+  if (e != hipSuccess) return e;
+  if (st != hipStreamCaptureStatusActive || g == nullptr) return hipErrorInvalidValue;
+  hipGraphNode_t node;
+  if ((e = hipGraphAddEventRecordNode(&node, g, deps, nd, ev)) != hipSuccess) return e;
+  return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+}
+
+// One local iteration on every partition: Yi = A_i^T (A_i Z_i).  When timing,
+// the local-multiply launch is bracketed by a pair of events: external event
+// nodes of the timed graph instance being captured, or plain event records.
 hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
   Ptrs p = ptrs(P);
   hipError_t e;
-  const bool timed = P->timing;
-  if (timed) {
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (P->timing && P->timing_slot >= 0) {
+    const int pair = P->timing_slot * kPairsPerSlot + P->timing_pair++;
+    ev0 = P->ev_pool[2 * pair];
+    ev1 = P->ev_pool[2 * pair + 1];
+    if ((e = capture_event_node(P->stream, ev0)) != hipSuccess) return e;
+  } else if (P->timing) {
     if (P->ev_used == kEvPairs && (e = drain_timing(P)) != hipSuccess) return e;
-    if ((e = hipEventRecord(P->ev_pool[2 * P->ev_used], P->stream)) != hipSuccess) return e;
+    ev0 = P->ev_pool[2 * P->ev_used];
+    ev1 = P->ev_pool[2 * P->ev_used + 1];
+    P->ev_used++;
+    if ((e = hipEventRecord(ev0, P->stream)) != hipSuccess) return e;
   }
   e = launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, p.tbuf, p.part, p.items,
                             P->stream);
   if (e != hipSuccess) return e;
-  if (timed) {
-    if ((e = hipEventRecord(P->ev_pool[2 * P->ev_used + 1], P->stream)) != hipSuccess) return e;
-    P->ev_used++;
+  if (ev1 != nullptr) {
+    e = (P->timing_slot >= 0) ? capture_event_node(P->stream, ev1) : hipEventRecord(ev1, P->stream);
+    if (e != hipSuccess) return e;
   }
-  return launch_reduce_partials(P->plan, k, p.part, p.slot_off, p.Yi, P->stream);
+  return launch_reduce_gram(P->plan, k, p.part, p.slot_off, p.Yi, p.gram, P->stream);
 }
 
 // Enqueue one communication round with p local steps (only kernel launches, so
@@ -253,12 +289,13 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
     if (l == p && p >= 2 && mode != LP_AGG_VANILLA) {
       // align the inputs of the last local step against the base node's
       const double* Zb = q.Zi + (int64_t)P->base * dk;
-      if ((e = launch_cross_gram(m, d, k, q.Zi, dk, Zb, 0, q.gram, s)) != hipSuccess) return e;
       if (mode == LP_AGG_SIGN) {
-        if ((e = launch_sign_from_gram(m, nch, k, q.gram, q.sgn, s)) != hipSuccess) return e;
-        if ((e = launch_apply_signs(m, d, k, q.Zi, q.sgn, q.Zw, P->plan.zw_bytes, s)) != hipSuccess)
+        if ((e = launch_diag_dot(m, d, k, q.Zi, Zb, q.gram, s)) != hipSuccess) return e;
+        if ((e = launch_sign_apply(m, d, k, q.gram, q.Zi, q.Zw, P->plan.zw_bytes, q.sgn, s)) !=
+            hipSuccess)
           return e;
       } else {
+        if ((e = launch_cross_gram(m, d, k, q.Zi, dk, Zb, 0, q.gram, s)) != hipSuccess) return e;
         if ((e = launch_procrustes(m, nch, k, q.gram, q.omat, q.flags + m + 1, s)) != hipSuccess)
           return e;
         if ((e = launch_right_mult(m, d, k, q.Zi, q.omat, (int64_t)k * k, false, nullptr, q.Zw,
@@ -268,12 +305,15 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
     }
     if ((e = local_iter(P, k, zsrc, zstride)) != hipSuccess) return e;
     if (l < p) {
-      if ((e = cholqr2(P->plan, P->ws, m, d, k, q.Yi, q.Zi, q.Zw, q.flags, s)) != hipSuccess)
+      if ((e = cholqr2_from_gram(P->plan, P->ws, m, d, k, q.Yi, q.Zi, q.Zw, q.flags, s)) !=
+          hipSuccess)
         return e;
     }
   }
-  if ((e = launch_aggregate(m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, s)) != hipSuccess) return e;
-  if ((e = cholqr2(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + m, s)) != hipSuccess)
+  if ((e = launch_aggregate_gram(m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, q.gram, s)) != hipSuccess)
+    return e;
+  if ((e = cholqr2_from_gram(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + m, s)) !=
+      hipSuccess)
     return e;
   if (hist) {
     if ((e = launch_sin_theta(d, k, q.Z, q.Uref, nullptr, q.hist, q.ctr, s)) != hipSuccess) return e;
@@ -281,23 +321,28 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
   return hipSuccess;
 }
 
-lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool use_graph) {
+lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool use_graph,
+                    int slot) {
   if (!use_graph) {
     LP_HIP(enqueue_round(P, k, p, mode, hist));
     return LP_OK;
   }
-  GraphKey key{k, p, (int)mode, hist ? 1 : 0};
+  GraphKey key{k, p, (int)mode, hist ? 1 : 0, slot};
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
     LP_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    P->timing_slot = slot;
+    P->timing_pair = 0;
     hipError_t e = enqueue_round(P, k, p, mode, hist);
+    P->timing_slot = -1;
     hipError_t e2 = hipStreamEndCapture(P->stream, &g);
-    if (e != hipSuccess) {
+    if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return fail(LP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+      (void)hipGetLastError();
+      return fail(LP_EDEVICE, std::string("capture: ") +
+                                  hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    if (e2 != hipSuccess) return fail(LP_EDEVICE, std::string("end capture: ") + hipGetErrorString(e2));
     hipGraphExec_t ex = nullptr;
     hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -306,6 +351,25 @@ lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool us
   }
   LP_HIP(hipGraphLaunch(it->second, P->stream));
   return LP_OK;
+}
+
+// Sum the event pairs of the timed graph instances replayed since the last harvest.
+hipError_t harvest_slots(lp_problem* P, std::vector<std::pair<int, int>>& pending) {
+  if (pending.empty()) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(P->stream);
+  if (e != hipSuccess) return e;
+  for (auto& sp : pending) {
+    for (int j = 0; j < sp.second; ++j) {
+      const int pair = sp.first * kPairsPerSlot + j;
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, P->ev_pool[2 * pair], P->ev_pool[2 * pair + 1]);
+      if (e != hipSuccess) return e;
+      P->ms_local += ms;
+      P->local_launches++;
+    }
+  }
+  pending.clear();
+  return hipSuccess;
 }
 
 // Make the problem's own stream wait for the caller's stream.
@@ -456,7 +520,7 @@ lp_status lp_destroy(lp_problem* P) {
 lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
     return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
-  if (t->local_kernel < 0 || t->local_kernel > 8) return fail(LP_EINVAL, "local_kernel out of range");
+  if (t->local_kernel < 0 || t->local_kernel > 6) return fail(LP_EINVAL, "local_kernel out of range");
   int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
   if (cr % 16 != 0 || cr < P->plan.min_chunk_rows)
     return fail(LP_EINVAL, "chunk_rows must be a multiple of 16 and >= the default");
@@ -470,8 +534,9 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
     P->plan.path = LocalPath::TwoPass;
   } else if (fused_ok) {
     P->plan.path = LocalPath::Mfma32;
-    P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 0;
+    P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 1;
   }
+  P->plan.nt_loads = t->cached_loads == 0;
   build_items(&P->plan, P->offsets.data(), cr);
   return upload_items(P);
 }
@@ -481,7 +546,120 @@ lp_status lp_get_tuning(lp_problem* P, lp_tuning* t) {
   t->struct_size = sizeof(lp_tuning);
   t->local_kernel = P->plan.path == LocalPath::TwoPass ? 1 : 2 + P->plan.variant;
   t->chunk_rows = P->plan.chunk_rows;
+  t->cached_loads = P->plan.nt_loads ? 0 : 1;
+  t->reserved = 0;
   return LP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string tune_key(lp_problem* P, int k) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream os;
+  os << arch << "|" << (int)P->dtype << "|" << P->n << "|" << P->d << "|" << P->m << "|" << k << "|"
+     << P->lda;
+  return os.str();
+}
+
+bool cache_lookup(const std::string& path, const std::string& key, lp_tuning* t) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {  // the last entry for a key wins
+    const size_t eq = line.find('=');
+    if (eq == std::string::npos || line.substr(0, eq) != key) continue;
+    int lk = 0, cached = 0;
+    long long cr = 0;
+    if (std::sscanf(line.c_str() + eq + 1, "%d,%lld,%d", &lk, &cr, &cached) == 3) {
+      t->struct_size = sizeof(lp_tuning);
+      t->local_kernel = lk;
+      t->chunk_rows = cr;
+      t->cached_loads = cached;
+      t->reserved = 0;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void cache_store(const std::string& path, const std::string& key, const lp_tuning& t) {
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << "=" << t.local_kernel << "," << (long long)t.chunk_rows << "," << t.cached_loads << "\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tuning* chosen) {
+  if (P == nullptr) return fail(LP_EINVAL, "problem is NULL");
+  lp_status st = check_k(P, k);
+  if (st != LP_OK) return st;
+  std::string path = cache_path ? cache_path : "";
+  if (path.empty()) {
+    const char* env = std::getenv("LP_AUTOTUNE_CACHE");
+    if (env != nullptr) path = env;
+  }
+  const std::string key = tune_key(P, k);
+  lp_tuning best;
+  std::memset(&best, 0, sizeof(best));
+  best.struct_size = sizeof(lp_tuning);
+  if (!path.empty() && cache_lookup(path, key, &best)) {
+    if ((st = lp_set_tuning(P, &best)) != LP_OK) return st;
+    if (chosen) *chosen = best;
+    return LP_OK;
+  }
+  const bool fused_ok = mfma32_eligible(P->dtype, P->d, P->lda, k) && P->k_max >= 16;
+  std::vector<lp_tuning> cand;
+  const int64_t c0 = P->plan.min_chunk_rows;
+  for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
+    if (fused_ok) {
+      for (int lk = 2; lk <= 6; ++lk)
+        for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, 0});
+    } else {
+      cand.push_back({(int32_t)sizeof(lp_tuning), 1, cr, 0, 0});
+    }
+  }
+  if ((st = join_in(P)) != LP_OK) return st;
+  Ptrs q = ptrs(P);
+  LP_HIP(launch_fill_i32((int32_t*)q.Zw_shared, (int)(P->d * k * P->plan.zw_bytes / 4), 0, P->stream));
+  hipEvent_t e0, e1;
+  LP_HIP(hipEventCreate(&e0));
+  LP_HIP(hipEventCreate(&e1));
+  double best_ms = 1e300;
+  for (const lp_tuning& c : cand) {
+    if ((st = lp_set_tuning(P, &c)) != LP_OK) break;
+    hipError_t e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part,
+                                         q.items, P->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, P->stream);
+    for (int it = 0; it < 3 && e == hipSuccess; ++it)
+      e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
+                                P->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, P->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = fail(LP_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LP_OK) return st;
+  if ((st = lp_set_tuning(P, &best)) != LP_OK) return st;
+  if (!path.empty()) cache_store(path, key, best);
+  if (chosen) *chosen = best;
+  return join_out(P);
 }
 
 lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp_agg mode,
@@ -506,7 +684,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   }
   const bool hist = o.U_ref != nullptr && o.sin_hist != nullptr;
   const bool timing = o.time_local != 0;
-  const bool graph = o.use_graph != 0 && !timing;
+  const bool graph = o.use_graph != 0;
   if (timing && P->ev_pool.empty()) {
     P->ev_pool.assign(2 * kEvPairs, nullptr);
     for (auto& ev : P->ev_pool) LP_HIP(hipEventCreate(&ev));
@@ -531,15 +709,38 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     LP_HIP(cholqr2(P->plan, P->ws, 1, d, k, Y0, q.Z, q.Zw_shared, q.flags + m, s));
   }
   LP_HIP(hipEventRecord(P->ev_t0, s));
-  int rounds = 0, iters = 0, hist_done = 0;
+  int rounds = 0, iters = 0, hist_done = 0, graph_rounds = 0;
   P->timing = timing;
+  std::vector<std::pair<int, int>> pending;  // (slot, p) of timed graph rounds not yet harvested
   for (int r = 0; r < T; ++r) {
     const int p = p_sched[r];
-    st = run_round(P, k, p, mode, hist, graph);
+    const bool timed_graph = timing && graph && P->timed_graphs_ok && p <= kPairsPerSlot;
+    // the two timing forms share the event pool: finish one before using the other
+    if (timed_graph && P->ev_used > 0) LP_HIP(drain_timing(P));
+    if (!timed_graph && timing && !pending.empty()) LP_HIP(harvest_slots(P, pending));
+    if (timed_graph) {
+      const int slot = (int)pending.size();
+      st = run_round(P, k, p, mode, hist, true, slot);
+      if (st != LP_OK) {
+        // the runtime refused the captured event records: time with plain launches
+        // (the refusal stays readable through lp_last_error)
+        P->timed_graphs_ok = false;
+        LP_HIP(harvest_slots(P, pending));
+        st = run_round(P, k, p, mode, hist, false, -1);
+      } else {
+        pending.emplace_back(slot, p);
+        graph_rounds++;
+      }
+    } else {
+      st = run_round(P, k, p, mode, hist, graph && !timing, -1);
+      if (graph && !timing) graph_rounds++;
+    }
     if (st != LP_OK) {
       P->timing = false;
       return st;
     }
+    if ((int)pending.size() == kTimedSlots || (r == T - 1 && !pending.empty()))
+      LP_HIP(harvest_slots(P, pending));
     rounds++;
     iters += p;
     if (o.signs_out != nullptr) {
@@ -590,7 +791,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     stats->bytes_A = (double)iters * (double)P->n * (double)P->d * (double)elem_bytes(P->dtype);
     stats->ms_local = P->ms_local;
     stats->local_launches = P->local_launches;
-    stats->reserved = 0;
+    stats->graph_rounds = graph_rounds;
   }
   if (breakdowns) return fail(LP_EBREAKDOWN, "Cholesky breakdown in an orthonormalisation");
   return LP_OK;
@@ -663,6 +864,36 @@ lp_status lp_bandwidth_probe(const void* buf, size_t bytes, int32_t iters, doubl
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return fail(LP_EDEVICE, std::string("bandwidth probe: ") + hipGetErrorString(err));
+  *gbs_out = best;
+  return LP_OK;
+}
+
+lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters, double* gbs_out,
+                        void* stream) {
+  if (dst == nullptr || src == nullptr || gbs_out == nullptr || bytes < 16 || (bytes % 16) != 0 ||
+      iters < 1 || ((uintptr_t)dst & 15) != 0 || ((uintptr_t)src & 15) != 0)
+    return fail(LP_EINVAL, "need 16-byte aligned buffers, bytes a multiple of 16, iters >= 1");
+  const char* d0 = (const char*)dst;
+  const char* s0 = (const char*)src;
+  if (d0 < s0 + bytes && s0 < d0 + bytes) return fail(LP_EINVAL, "src and dst overlap");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  LP_HIP(hipEventCreate(&e0));
+  LP_HIP(hipEventCreate(&e1));
+  double best = 0.0;
+  hipError_t err = hipSuccess;
+  for (int it = 0; it < iters && err == hipSuccess; ++it) {
+    err = hipEventRecord(e0, s);
+    if (err == hipSuccess) err = launch_stream_copy(dst, src, bytes, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms > 0.f) best = std::max(best, 2.0 * (double)bytes / (ms * 1e-3) / 1e9);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(LP_EDEVICE, std::string("copy probe: ") + hipGetErrorString(err));
   *gbs_out = best;
   return LP_OK;
 }

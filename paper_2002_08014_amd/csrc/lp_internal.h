@@ -14,7 +14,7 @@
 namespace lp {
 
 constexpr int kMaxK = 64;        // largest iteration rank supported by the kernels
-constexpr int kGramRows = 256;   // rows of a d x k matrix per Gram partial
+constexpr int kGramRows = 64;    // rows of a d x k matrix per Gram partial
 constexpr int kBlock = 256;      // threads per workgroup for the small kernels
 
 // A contiguous row range of one partition processed by one workgroup of the
@@ -31,8 +31,8 @@ enum class LocalPath : int { TwoPass = 0, Mfma32 = 1 };
 
 struct Layout {
   // byte offsets into the workspace
-  size_t Zi, Zw, Yi, tmp, Z, Zw_shared, Y, Uref, part, tbuf, gram, rinv, omat, sgn, flags, items,
-      slot_off, hist, ctr, scal, total;
+  size_t Zi, Zw, Yi, tmp, Z, Zw_shared, Y, Uref, part, tbuf, gram, gram2, rinv, omat, sgn, flags,
+      items, slot_off, hist, ctr, scal, total;
 };
 
 constexpr int kHistCap = 1024;  // rounds of sin-theta history buffered on the device
@@ -49,7 +49,8 @@ struct Plan {
   size_t acc_bytes;          // 8 for FP64 A, 4 otherwise
   size_t zw_bytes;           // bytes per element of the working copy of Z
   LocalPath path;
-  int32_t variant;           // fused kernel variant: 0 two WGs/CU, 1 one WG/CU, 2 one WG/CU + 2 tiles ahead
+  int32_t variant;           // fused kernel variant (see k_mfma.hip)
+  bool nt_loads;             // nontemporal loads of A in the fused kernel
   int64_t min_chunk_rows;    // the default chunking the workspace was sized for
   Layout L;
 };
@@ -61,14 +62,18 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
                int32_t k_max, Plan* plan, std::string* err);
 
 struct GraphKey {
-  int32_t k, p, mode, hist;
+  int32_t k, p, mode, hist, slot;  // slot >= 0: timed instance with its own event pairs
   bool operator<(const GraphKey& o) const {
     if (k != o.k) return k < o.k;
     if (p != o.p) return p < o.p;
     if (mode != o.mode) return mode < o.mode;
-    return hist < o.hist;
+    if (hist != o.hist) return hist < o.hist;
+    return slot < o.slot;
   }
 };
+
+constexpr int kTimedSlots = 8;      // timed graph instances replayed before one harvest
+constexpr int kPairsPerSlot = 32;   // local-multiply event pairs per timed instance
 
 }  // namespace lp
 
@@ -90,6 +95,9 @@ struct lp_problem {
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
   bool timing = false;
+  int timing_slot = -1;   // >= 0 while capturing a timed graph instance
+  int timing_pair = 0;
+  bool timed_graphs_ok = true;
   double ms_local = 0.0;
   int local_launches = 0;
 };
@@ -175,9 +183,49 @@ hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
 
 // Read `bytes` (a multiple of 16) of `buf` once with 128-bit loads.
 hipError_t launch_stream_read(const void* buf, size_t bytes, hipStream_t s);
+// Copy `bytes` (a multiple of 16) from src to dst with the same streaming pattern.
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Address of the library's one-double device result slot used by lp_sin_theta.
 hipError_t sin_slot_address(double** p);
+
+// Y_i = sum of partials (item order, FP64) and the Gram partials of Y_i's row
+// chunks (kGramRows rows) into gram; grid over (row chunks, partitions).
+hipError_t launch_reduce_gram(const Plan& P, int k, const void* part, const int32_t* slot_off,
+                              double* Yi, double* gram, hipStream_t s);
+
+// Y = scale * sum_i Yi and the Gram partials of Y's row chunks into gram.
+hipError_t launch_aggregate_gram(int m, int64_t d, int k, const double* Yi, double scale, double* Y,
+                                 double* gram, hipStream_t s);
+
+// One CholeskyQR pass from precomputed Gram partials: every workgroup sums the
+// partials of its matrix, factors G = R^T R (FP64), forms R^{-1} and writes
+// Q = X R^{-1} for its row chunk; optionally the working copy (zw) and the Gram
+// partials of Q (gram_out).  flags[b] = 1 on breakdown.
+hipError_t launch_chol_apply(int batch, int64_t d, int k, const double* X, const double* gram_in,
+                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
+                             int32_t* flags, hipStream_t s);
+
+// R^{-1} of chol(sum of Gram partials) per matrix, one wavefront each.
+hipError_t launch_chol_inv_wave(int batch, int nch, int k, const double* gram, double* rinv,
+                                int32_t* flags, hipStream_t s);
+
+// Q = X R^{-1} per row chunk (R^{-1} from rinv), optional working copy and Gram
+// partials of Q.
+hipError_t launch_apply_gram(int batch, int64_t d, int k, const double* X, const double* rinv,
+                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
+                             hipStream_t s);
+
+// Sign-fixing in two launches: column dots <Zi[:,j], Zb[:,j]> partials per row
+// chunk, then sum, sign (sgn(0) = +1), record sgn and flip Zi and its working copy.
+hipError_t launch_diag_dot(int batch, int64_t d, int k, const double* Zi, const double* Zb,
+                           double* part, hipStream_t s);
+hipError_t launch_sign_apply(int batch, int64_t d, int k, const double* part, double* Zi, void* zw,
+                             size_t zw_bytes, int8_t* sgn, hipStream_t s);
+
+// CholeskyQR2 when the Gram partials of Y are already in the plan's gram buffer.
+hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
+                             double* Q, void* zw, int32_t* flags, hipStream_t s);
 
 // CholeskyQR2: Q_b = orth(Y_b) for a batch of d x k FP64 matrices, using
 // gram/rinv scratch from the plan; also writes the working copy when zw != NULL.

@@ -12,7 +12,7 @@ from tests._util import host, sin_theta_np, upcast
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = (1, 2, 3, 4, 5, 6, 7, 8)   # two-pass, then the fused forms (see lp_tuning)
+VARIANTS = (1, 2, 3, 4, 5, 6)   # two-pass, then the fused forms (see lp_tuning)
 
 
 @pytest.fixture(scope="module")
@@ -32,18 +32,19 @@ def _check_partitions(Y, A, offsets, Zw, parts):
         assert np.all(err <= gamma * bound), (i, float(err.max()), float((gamma * bound).min()))
 
 
+@pytest.mark.parametrize("cached", [False, True])
 @pytest.mark.parametrize("d", [256, 512, 768, 1024])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_fused_small(lp, d, variant):
-    print(f"fused small d={d} variant={variant}", flush=True)
+def test_fused_small(lp, d, variant, cached):
+    print(f"fused small d={d} variant={variant} cached={cached}", flush=True)
     n, m = 3 * d + 37, 3
     w = synth.make_small(n, d, 16, m, seed=d, dtype=torch.float32, uneven=True)
     A_dev = w.A.to("cuda:0")
     A = upcast(A_dev)
     P = lp.lp_create(A_dev, w.offsets, 16)
-    lp.lp_set_tuning(P, variant, 0)
+    lp.lp_set_tuning(P, variant, 0, cached)
     t = lp.lp_get_tuning(P)
-    assert t["local_kernel"] == variant
+    assert t["local_kernel"] == variant and t["cached_loads"] == cached
     Z = oracle.orth(np.random.default_rng(d).standard_normal((d, 16)))
     Y = host(lp.lp_local_multiply(P, 16, torch.as_tensor(Z)))
     _check_partitions(Y, A, w.offsets, Z.astype(np.float32).astype(np.float64), range(m))
@@ -99,3 +100,22 @@ def test_full_size_run_parity(lp, c2):
     assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
     assert ro["ambiguous"] == 0
     assert np.array_equal(r["signs"], np.stack(ro["signs"]))
+
+
+def test_autotune_applies_a_valid_choice(lp, tmp_path):
+    """The autotuner picks one of the candidates, caches it, and the result of
+    the chosen kernel still meets the parity bound."""
+    print("autotune", flush=True)
+    w = synth.make_small(4096, 512, 16, 4, seed=3, dtype=torch.float32)
+    A_dev = w.A.to("cuda:0")
+    P = lp.lp_create(A_dev, w.offsets, 16)
+    cache = str(tmp_path / "tune.txt")
+    t = lp.lp_autotune(P, 16, cache)
+    assert 2 <= t["local_kernel"] <= 6 and t["chunk_rows"] % 16 == 0
+    assert lp.lp_get_tuning(P)["local_kernel"] == t["local_kernel"]
+    assert open(cache).read().count("=") == 1
+    P2 = lp.lp_create(A_dev, w.offsets, 16)
+    assert lp.lp_autotune(P2, 16, cache) == t          # served from the cache
+    Z = oracle.orth(np.random.default_rng(4).standard_normal((512, 16)))
+    Y = host(lp.lp_local_multiply(P, 16, torch.as_tensor(Z)))
+    _check_partitions(Y, upcast(A_dev), w.offsets, Z.astype(np.float32).astype(np.float64), range(4))

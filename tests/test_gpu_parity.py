@@ -268,3 +268,21 @@ def test_create_right_after_queued_work(lib):
         r = lib.lp_run(P, 16, w.p_sched, "sign", w.Y0)
     ro = oracle.localpower(upcast(A_dev), w.offsets, 16, w.p_sched, "sign", w.Y0)
     assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
+
+
+def test_timed_graph_rounds(lib, c1):
+    """Timing the local multiply inside replayed graphs changes nothing in the
+    result, times every launch, and keeps the rounds on graphs."""
+    w, A, U, lam = c1
+    _flush("timed graphs")
+    sched = synth.decay_schedule((8, 4, 2, 1), 5)
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    r0 = lib.lp_run(P, w.k, sched, "sign", w.Y0, use_graph=False)
+    r1 = lib.lp_run(P, w.k, sched, "sign", w.Y0, time_local=True)
+    r2 = lib.lp_run(P, w.k, sched, "sign", w.Y0, time_local=True, use_graph=False)
+    assert torch.equal(r0["Z"], r1["Z"]) and torch.equal(r0["Z"], r2["Z"])
+    for r in (r1, r2):
+        st = r["stats"]
+        assert st["local_launches"] == sum(sched) and st["ms_local"] > 0
+    assert r1["stats"]["graph_rounds"] == len(sched)
+    assert r2["stats"]["graph_rounds"] == 0
