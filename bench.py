@@ -88,6 +88,27 @@ def cpu_baseline(A_dev, offsets, k, Y0, budget_s=12.0):
                       f"storage like the GPU figure"}
 
 
+def rounds_to(hist, thresholds=(1e-1, 1e-2, 1e-3, 1e-6)):
+    out = {}
+    for th in thresholds:
+        hit = [i + 1 for i, v in enumerate(hist) if v <= th]
+        out[f"{th:.0e}"] = hit[0] if hit else None
+    return out
+
+
+def convergence(lp, P, w, k):
+    """Rounds to sin theta thresholds for p = 1, p = 4 (sign, OPT) and a decaying p, against
+    the subspace of a long p = 1 run refined by Rayleigh-Ritz (the FP32 fixed point)."""
+    ref = lp.lp_run(P, k, [1] * 150, "sign", w.Y0, ritz=True)["Z"]
+    runs = {"p1": ([1] * 60, "sign"), "p4_sign": ([4] * 50, "sign"), "p4_opt": ([4] * 50, "opt"),
+            "decay_4_2_1_x10": ([4] * 10 + [2] * 10 + [1] * 40, "sign")}
+    out = {}
+    for name, (sched, mode) in runs.items():
+        h = lp.lp_run(P, k, sched, mode, w.Y0, U_ref=ref)["sin_hist"]
+        out[name] = {"rounds_to": rounds_to(h), "final": float(h[-1]), "rounds": len(sched)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +117,7 @@ def main():
     ap.add_argument("--rounds", type=int, default=50)
     ap.add_argument("--mode", default="sign", choices=["sign", "opt", "vanilla"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-convergence", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the m LocalPower nodes are partitions on a single "
@@ -165,6 +187,9 @@ def main():
                      "traffic": traffic, "kernel_ms": round(k1_ms, 5), "launches": launches,
                      "measured_read_gbs": round(read_gbs, 1), "measured_copy_gbs": round(copy_gbs, 1)},
     }
+    if not args.no_convergence:
+        log("convergence (rounds to sin theta thresholds)")
+        out["convergence"] = convergence(lp, P, w, k)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(w.A, w.offsets, k, w.Y0)

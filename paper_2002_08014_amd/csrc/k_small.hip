@@ -375,6 +375,108 @@ apply_gram_kernel(int64_t d, int k, const double* __restrict__ X, const double* 
   }
 }
 
+
+// Cholesky G = R^T R (upper R, positive diagonal) of the k x k LDS matrix G by
+// the first wavefront (lane c holds column c; rows broadcast with readlane),
+// written to the LDS matrix R, with 1/R_jj in rdi.  On breakdown *bad is set
+// and R is the identity.  Call from all threads; ends with a block barrier.
+template <int KM>
+__device__ void chol_wave(const double* G, double* R, double* rdi, int k, int* bad) {
+  if (threadIdx.x < 64) {
+    const int c = threadIdx.x;
+    double g[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) g[i] = (c < k && i < k) ? G[i * k + c] : 0.0;
+    bool badw = false;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (j < k) {
+        double djj = rdlane(g[j], j);
+        if (!(djj > 0.0) || !isfinite(djj)) {
+          badw = true;
+          djj = 1.0;
+        }
+        const double rjj = sqrt(djj);
+        const double inv = 1.0 / rjj;
+        const double rjc = (c == j) ? rjj : ((c > j && c < k) ? g[j] * inv : 0.0);
+        if (c < k) R[j * k + c] = rjc;
+        if (c == j) rdi[j] = inv;
+#pragma unroll
+        for (int i = j + 1; i < KM; ++i) {
+          if (i < k) {
+            const double rji = rdlane(rjc, i);
+            if (c >= i) g[i] -= rji * rjc;
+          }
+        }
+      }
+    }
+    if (badw) {
+      for (int e = c; e < k * k; e += 64) R[e] = (e / k == e % k) ? 1.0 : 0.0;
+      if (c < k) rdi[c] = 1.0;
+      if (c == 0) *bad = 1;
+    }
+  }
+  __syncthreads();
+}
+
+// Rows per CholeskyQR chunk so that the chunk's rows fit a 32 KB LDS block.
+template <int KM>
+struct ChunkRows {
+  static constexpr int value = (32768 / 8) / KM;  // 256 for k <= 16, 128 for 32, 64 for 64
+};
+
+// grid (ceil(d / RC), batch): one CholeskyQR pass for a row chunk: sum the nch_in
+// Gram partials of matrix b, Cholesky-factor them (every workgroup redundantly,
+// in one wavefront), forward-substitute Q_row = X_row R^{-1} (one thread per
+// row), and optionally write the working copy and the Gram partial of the
+// chunk's rows (chunk = RC rows, partial index b * gridDim.x + c).
+template <typename TW, int KM>
+__global__ void __launch_bounds__(kBlock)
+chol_solve_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
+                  const double* __restrict__ gin, double* __restrict__ Q, TW* __restrict__ zw,
+                  double* __restrict__ gout, int32_t* __restrict__ flags) {
+  constexpr int RC = ChunkRows<KM>::value;
+  __shared__ double G[KM * KM];
+  __shared__ double R[KM * KM];
+  __shared__ double rdi[KM];
+  __shared__ double qs[RC * KM];
+  __shared__ int bad;
+  const int b = blockIdx.y, c = blockIdx.x, nch_out = gridDim.x;
+  if (threadIdx.x == 0) bad = 0;
+  sum_partials(gin, b, nch_in, k, G);
+  __syncthreads();
+  chol_wave<KM>(G, R, rdi, k, &bad);
+  const int64_t r0 = (int64_t)c * RC;
+  const int rows = (int)min<int64_t>(RC, d - r0);
+  for (int rr = threadIdx.x; rr < rows; rr += kBlock) {
+    const double* xr = X + (int64_t)b * d * k + (r0 + rr) * k;
+    double q[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (j < k) {
+        double v = xr[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) v = fma(-q[l], R[l * k + j], v);
+        q[j] = v * rdi[j];
+      }
+    }
+    double* qo = Q + (int64_t)b * d * k + (r0 + rr) * k;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (j < k) {
+        qo[j] = q[j];
+        if (zw != nullptr) zw[(int64_t)b * d * k + (r0 + rr) * k + j] = (TW)q[j];
+        qs[rr * k + j] = q[j];
+      }
+    }
+  }
+  if (gout != nullptr) {
+    __syncthreads();
+    gram_block<KM>(qs, rows, k, gout + ((int64_t)b * nch_out + c) * k * k);
+  }
+  if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
+}
+
 // grid (nch, batch): partial column dots of chunk c: part[(b*nch + c)*k + j].
 __global__ void __launch_bounds__(kBlock)
 diag_dot_kernel(int64_t d, int k, const double* __restrict__ Zi, const double* __restrict__ Zb,
@@ -958,6 +1060,37 @@ hipError_t launch_apply_gram(int batch, int64_t d, int k, const double* X, const
   else
     apply_gram_t<float>(grid, d, k, X, rinv, Q, (float*)zw, gram_out, s);
   return hipGetLastError();
+}
+
+
+template <typename TW>
+static hipError_t chol_solve_t(int batch, int64_t d, int k, int nch_in, const double* X,
+                               const double* gin, double* Q, TW* zw, double* gout, int32_t* flags,
+                               hipStream_t s) {
+  if (k <= 16) {
+    dim3 grid(nblk(d, ChunkRows<16>::value), batch);
+    chol_solve_kernel<TW, 16><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
+  } else if (k <= 32) {
+    dim3 grid(nblk(d, ChunkRows<32>::value), batch);
+    chol_solve_kernel<TW, 32><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
+  } else {
+    dim3 grid(nblk(d, ChunkRows<kMaxK>::value), batch);
+    chol_solve_kernel<TW, kMaxK><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
+  }
+  return hipGetLastError();
+}
+
+int chol_solve_chunks(int64_t d, int k) {
+  const int rc = k <= 16 ? ChunkRows<16>::value : (k <= 32 ? ChunkRows<32>::value : ChunkRows<kMaxK>::value);
+  return nblk(d, rc);
+}
+
+hipError_t launch_chol_solve(int batch, int64_t d, int k, int nch_in, const double* X,
+                             const double* gram_in, double* Q, void* zw, size_t zw_bytes,
+                             double* gram_out, int32_t* flags, hipStream_t s) {
+  if (zw == nullptr || zw_bytes == 8)
+    return chol_solve_t<double>(batch, d, k, nch_in, X, gram_in, Q, (double*)zw, gram_out, flags, s);
+  return chol_solve_t<float>(batch, d, k, nch_in, X, gram_in, Q, (float*)zw, gram_out, flags, s);
 }
 
 hipError_t launch_diag_dot(int batch, int64_t d, int k, const double* Zi, const double* Zb,

@@ -151,17 +151,16 @@ hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int 
   const Layout& L = P.L;
   double* gram = (double*)(ws + L.gram);
   double* gram2 = (double*)(ws + L.gram2);
-  double* rinv = (double*)(ws + L.rinv);
   double* tmp = (double*)(ws + L.tmp);
   const int nch = (int)((d + kGramRows - 1) / kGramRows);
   hipError_t e;
   // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}, and the Gram partials of Q1
-  if ((e = launch_chol_inv_wave(batch, nch, k, gram, rinv, flags, s)) != hipSuccess) return e;
-  if ((e = launch_apply_gram(batch, d, k, Y, rinv, tmp, nullptr, 0, gram2, s)) != hipSuccess)
+  if ((e = launch_chol_solve(batch, d, k, nch, Y, gram, tmp, nullptr, 0, gram2, flags, s)) !=
+      hipSuccess)
     return e;
   // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1} (and the working copy)
-  if ((e = launch_chol_inv_wave(batch, nch, k, gram2, rinv, flags, s)) != hipSuccess) return e;
-  return launch_apply_gram(batch, d, k, tmp, rinv, Q, zw, P.zw_bytes, nullptr, s);
+  return launch_chol_solve(batch, d, k, chol_solve_chunks(d, k), tmp, gram2, Q, zw, P.zw_bytes,
+                           nullptr, flags, s);
 }
 
 hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y, double* Q,

@@ -216,6 +216,14 @@ hipError_t launch_apply_gram(int batch, int64_t d, int k, const double* X, const
                              double* Q, void* zw, size_t zw_bytes, double* gram_out,
                              hipStream_t s);
 
+// One CholeskyQR pass per row chunk: sum the nch_in Gram partials, factor (every
+// workgroup, one wavefront), forward-substitute the chunk's rows, optionally write
+// the working copy and the Gram partials of Q (chol_solve_chunks(d, k) of them).
+hipError_t launch_chol_solve(int batch, int64_t d, int k, int nch_in, const double* X,
+                             const double* gram_in, double* Q, void* zw, size_t zw_bytes,
+                             double* gram_out, int32_t* flags, hipStream_t s);
+int chol_solve_chunks(int64_t d, int k);
+
 // Sign-fixing in two launches: column dots <Zi[:,j], Zb[:,j]> partials per row
 // chunk, then sum, sign (sgn(0) = +1), record sgn and flip Zi and its working copy.
 hipError_t launch_diag_dot(int batch, int64_t d, int k, const double* Zi, const double* Zb,
