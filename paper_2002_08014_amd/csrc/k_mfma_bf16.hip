@@ -1,0 +1,252 @@
+// Fused single-pass local multiply on CDNA4 matrix cores for BF16 A
+// (k = 16 or 32, d in {512, 1024, 1536, 2048}).
+//
+// Computes, for one work item (a contiguous row range of partition i),
+//   part = A_rows^T bf16(A_rows bf16(Z_i))      (Eq. (power_yi) without 1/s_i)
+// reading every element of A once from HBM.  Both products run on BF16
+// matrix-core instructions with FP32 accumulation; Z_i and the intermediate
+// t = A_rows Z_i are rounded to BF16 (round to nearest even) as operands.
+//
+// Layout: W waves (4 or 8), wave w owns the column slice [w*d/W, (w+1)*d/W) of
+// every 16-row tile; NC = d/(32 W) 32-column chunks per slice.
+//   * A tiles are copied HBM -> LDS by direct-to-LDS loads (no registers), two
+//     tile buffers per wave; each wave reads only its own slice, so the only
+//     cross-wave traffic is the t reduction.  LDS row r of a wave tile holds
+//     the slice's 16-byte chunks XOR-swizzled by s(r) = (2r + r/8) mod 16,
+//     which keeps both read patterns below free of bank conflicts.
+//   * product 1 (v_mfma_f32_16x16x32_bf16, per chunk c and 16-wide k block):
+//     M = tile row (lane%16), K = 8 consecutive columns 32c + 8(lane/16) + e,
+//     read as one 128-bit LDS load per lane; Z_i sits in registers in the
+//     matching B-operand layout for the whole work item.
+//   * the W per-slice partial t's (FP32) are summed through LDS in a fixed
+//     order, rounded to BF16 and stored as t^T (k-major), so each lane's
+//     product-2 B operand is one 64-bit LDS load.
+//   * product 2 (v_mfma_f32_16x16x16_bf16, per 16-column block): the A operand
+//     is the transposed tile block, read with ds_read_b64_tr_b16 (lane
+//     16g + 4f + q loads 4 columns of row 4g + f; the transpose hands lane
+//     16g + i column i of rows 4g..4g+3), K = tile rows; the Y partial for
+//     the slice lives in accumulators for the whole work item.
+#include "lp_internal.h"
+
+namespace lp {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(3))) s4 lds_s4;
+
+constexpr int kRows = 16;   // tile rows
+
+__device__ inline int bswz(int r) { return (2 * r + (r >> 3)) & 15; }
+
+__device__ inline uint16_t bf16_bits(float x) {
+  __bf16 h = (__bf16)x;   // round to nearest even
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+// Wait until at most N direct-to-LDS loads of this wave are outstanding; also a
+// compiler barrier, so no LDS read is moved above it.
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  if constexpr (N == 0)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// W: waves; NC: 32-column chunks per wave slice (d = 32 NC W); KT: 16-wide k
+// blocks (k = 16 KT); AUX: cache policy of the A loads (0 default, 2 nontemporal).
+template <int W, int NC, int KT, int AUX>
+__global__ void __launch_bounds__(64 * W, 1)
+k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
+             int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+  constexpr int K = 16 * KT;
+  constexpr int CW = 32 * NC;        // columns per wave slice
+  constexpr int RB = 2 * CW;         // bytes of one slice row
+  constexpr int TB = kRows * RB;     // bytes of one wave tile
+  constexpr int NI = TB / 1024;      // direct-to-LDS loads (1 KB each) per wave tile
+  constexpr int NCT = 2 * NC;        // 16-column blocks per slice
+  constexpr int D = W * CW;
+  static_assert(NC % 4 == 0 && TB % 1024 == 0, "slice must be a whole number of 256-byte groups");
+  __shared__ __attribute__((aligned(16))) unsigned char abuf[2][W][TB];
+  __shared__ f4 tpart[W][KT][64];
+  __shared__ __attribute__((aligned(16))) uint16_t tbf[K * kRows];   // t^T, k-major
+
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane >> 4;
+  const int i = lane & 15;
+  const int slice0 = w * CW;
+  const int rows = (int)it.rows;
+  const int ntiles = (rows + kRows - 1) / kRows;
+  const uint16_t* Ab = A + it.row0 * lda + slice0;
+
+  // start the first tile before anything else
+  auto issue = [&](int r0, int b) {
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const int byte = ii * 1024 + 16 * lane;
+      const int r = byte / RB;
+      const int p = (byte % RB) / 16;
+      const int gc = p ^ bswz(r);
+      const int row = min(r0 + r, rows - 1);   // rows past the item repeat the last one; their t is zeroed
+      const uint16_t* src = Ab + (int64_t)row * lda + 8 * gc;
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)&abuf[b][w][ii * 1024], 16, 0, AUX);
+    }
+  };
+  issue(0, 0);
+
+  // Z_i slice in B-operand layout: zb[c][kt][e] = Z[slice0 + 32c + 8g + e][16kt + i]
+  const float* Z = Zw + (int64_t)it.part * z_stride;
+  bf8 zb[NC][KT];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        zb[c][kt][e] = (__bf16)Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * K + 16 * kt + i];
+
+  f4 yacc[NCT][KT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) yacc[ct][kt] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // per-lane LDS byte offsets inside a wave tile
+  int off1[4];   // product 1, chunk c: 256 (c / 4) + off1[c % 4]
+#pragma unroll
+  for (int c = 0; c < 4; ++c) off1[c] = i * RB + 16 * ((4 * c + g) ^ bswz(i));
+  const int f = (lane >> 2) & 3, q = lane & 3;
+  const int tr_row = 4 * g + f;
+  int off2[8];   // product 2, block ct: 256 (ct / 8) + off2[ct % 8]
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    off2[c] = tr_row * RB + 16 * ((2 * c + (q >> 1)) ^ bswz(tr_row)) + 8 * (q & 1);
+
+  for (int j = 0; j < ntiles; ++j) {
+    const int b = j & 1;
+    if (j + 1 < ntiles) {
+      issue((j + 1) * kRows, b ^ 1);
+      wait_vm<NI>();
+    } else {
+      wait_vm<0>();
+    }
+    const unsigned char* tb = &abuf[b][w][0];
+
+    // product 1: partial t over this wave's slice (two chains per k block)
+    f4 tacc[KT][2];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) tacc[kt][0] = tacc[kt][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c0 = 0; c0 < NC; c0 += 4) {
+      bf8 a1[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a1[c] = *(const bf8*)(tb + 256 * (c0 / 4) + off1[c]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+          tacc[kt][c & 1] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[c], zb[c0 + c][kt], tacc[kt][c & 1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) tpart[w][kt][lane] = tacc[kt][0] + tacc[kt][1];
+    __syncthreads();
+
+    // sum the W slice partials (fixed order), round to BF16, store t^T;
+    // rows past the end of the item get t = 0
+    const int valid = min(kRows, rows - j * kRows);
+    // (k block, register) combination cb = kt*4 + r goes to wave cb % W
+#pragma unroll
+    for (int cb = w; cb < 4 * KT; cb += W) {
+      const int kt = cb >> 2, r = cb & 3;
+      float s = tpart[0][kt][lane][r];
+#pragma unroll
+      for (int v = 1; v < W; ++v) s += tpart[v][kt][lane][r];
+      const int row = 4 * g + r;
+      tbf[(i + 16 * kt) * kRows + row] = bf16_bits(row < valid ? s : 0.f);
+    }
+    __syncthreads();
+
+    // product 2: Y_slice += A_tile^T t
+    s4 tb_op[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) tb_op[kt] = *(const s4*)&tbf[(i + 16 * kt) * kRows + 4 * g];
+#pragma unroll
+    for (int c0 = 0; c0 < NCT; c0 += 8) {
+      s4 a2[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        a2[c] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_s4*)(tb + 256 * (c0 / 8) + off2[c]));
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+          yacc[c0 + c][kt] =
+              __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[c], tb_op[kt], yacc[c0 + c][kt], 0, 0, 0);
+    }
+  }
+  // yacc[ct][kt][r] = Y[slice0 + 16ct + 4g + r][16kt + i]
+  float* o = part + (int64_t)it.slot * D * K;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * K + 16 * kt + i] = yacc[ct][kt][r];
+}
+
+template <int W, int NC, int KT>
+hipError_t launch_nc(int nitems, bool nt, const uint16_t* a, int64_t lda, const float* z,
+                     int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+  if (nt)
+    k1_mfma_bf16<W, NC, KT, 2><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+  else
+    k1_mfma_bf16<W, NC, KT, 0><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+  return hipGetLastError();
+}
+
+// variant 0: four waves (any eligible d); variant 1: eight waves (d = 1024 or 2048)
+template <int KT>
+hipError_t launch_kt(int64_t d, int variant, int nitems, bool nt, const uint16_t* a, int64_t lda,
+                     const float* z, int64_t z_stride, const WorkItem* items, float* o,
+                     hipStream_t s) {
+  if (variant == 1 && d == 1024) return launch_nc<8, 4, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  if (variant == 1 && d == 2048) return launch_nc<8, 8, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  switch (d) {
+    case 512: return launch_nc<4, 4, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 1024: return launch_nc<4, 8, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 1536: return launch_nc<4, 12, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 2048: return launch_nc<4, 16, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A) {
+  return dtype == LP_BF16 && (k == 16 || k == 32) &&
+         (d == 512 || d == 1024 || d == 1536 || d == 2048) && (lda % 8) == 0 &&
+         ((uintptr_t)A % 16) == 0;
+}
+
+hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
+                                        const void* Zw, int64_t z_stride, void* part,
+                                        const WorkItem* items, hipStream_t s) {
+  const int nitems = (int)P.items.size();
+  const uint16_t* a = (const uint16_t*)A;
+  const float* z = (const float*)Zw;
+  float* o = (float*)part;
+  if (k == 32) return launch_kt<2>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+  return launch_kt<1>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+}
+
+}  // namespace lp

@@ -143,6 +143,8 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
                                  const WorkItem* items_dev, hipStream_t s) {
   if (P.path == LocalPath::Mfma32 && mfma32_eligible(P.dtype, P.d, lda, k))
     return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, s);
+  if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A))
+    return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, s);
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
 }
 
@@ -372,6 +374,22 @@ hipError_t harvest_slots(lp_problem* P, std::vector<std::pair<int, int>>& pendin
 }
 
 // Make the problem's own stream wait for the caller's stream.
+// The fused kernel family this problem can use (TwoPass when none applies).
+LocalPath fused_kind(const lp_problem* P) {
+  if (P->k_max >= 16 && mfma32_eligible(P->dtype, P->d, P->lda, 16)) return LocalPath::Mfma32;
+  if (P->k_max >= 16 && mfma16_eligible(P->dtype, P->d, P->lda, 16, P->A)) return LocalPath::MfmaBf16;
+  return LocalPath::TwoPass;
+}
+
+// Whether the fused kernel handles this k.
+bool fused_for_k(const lp_problem* P, int k) {
+  switch (fused_kind(P)) {
+    case LocalPath::Mfma32: return mfma32_eligible(P->dtype, P->d, P->lda, k);
+    case LocalPath::MfmaBf16: return mfma16_eligible(P->dtype, P->d, P->lda, k, P->A);
+    default: return false;
+  }
+}
+
 lp_status join_in(lp_problem* P) {
   LP_HIP(hipEventRecord(P->ev_join_in, P->user_stream));
   LP_HIP(hipStreamWaitEvent(P->stream, P->ev_join_in, 0));
@@ -460,7 +478,6 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
     return fail(LP_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
   }
   P->plan.lda = lda;
-  if (mfma32_eligible(dtype, d, lda, 16) && k_max >= 16) P->plan.path = LocalPath::Mfma32;
   P->A = A;
   P->dtype = dtype;
   P->n = n;
@@ -468,6 +485,8 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
   P->lda = lda;
   P->m = m;
   P->k_max = k_max;
+  P->plan.path = fused_kind(P);
+  if (P->plan.path == LocalPath::MfmaBf16) P->plan.variant = 0;
   P->offsets.assign(offsets, offsets + m + 1);
   P->base = 0;
   for (int i = 1; i < m; ++i)
@@ -520,6 +539,8 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
     return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
   if (t->local_kernel < 0 || t->local_kernel > 6) return fail(LP_EINVAL, "local_kernel out of range");
+  if (t->local_kernel > 3 && fused_kind(P) == LocalPath::MfmaBf16)
+    return fail(LP_EINVAL, "the BF16 fused kernel has two variants (local_kernel 2, 3)");
   int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
   if (cr % 16 != 0 || cr < P->plan.min_chunk_rows)
     return fail(LP_EINVAL, "chunk_rows must be a multiple of 16 and >= the default");
@@ -528,12 +549,16 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   LP_HIP(hipStreamSynchronize(P->stream));
   for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
   P->graphs.clear();
-  const bool fused_ok = mfma32_eligible(P->dtype, P->d, P->lda, 16) && P->k_max >= 16;
-  if (t->local_kernel == 1 || (t->local_kernel >= 2 && !fused_ok)) {
+  const LocalPath fk = fused_kind(P);
+  if (t->local_kernel == 1 || (t->local_kernel >= 2 && fk == LocalPath::TwoPass)) {
     P->plan.path = LocalPath::TwoPass;
-  } else if (fused_ok) {
-    P->plan.path = LocalPath::Mfma32;
+  } else if (fk == LocalPath::Mfma32) {
+    P->plan.path = fk;
     P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 1;
+  } else if (fk == LocalPath::MfmaBf16) {
+    P->plan.path = fk;
+    const bool w8 = P->d == 1024 || P->d == 2048;   // the eight-wave form needs these widths
+    P->plan.variant = (t->local_kernel == 3 && w8) ? 1 : 0;
   }
   P->plan.nt_loads = t->cached_loads == 0;
   build_items(&P->plan, P->offsets.data(), cr);
@@ -613,12 +638,13 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
     if (chosen) *chosen = best;
     return LP_OK;
   }
-  const bool fused_ok = mfma32_eligible(P->dtype, P->d, P->lda, k) && P->k_max >= 16;
+  const bool fused_ok = fused_for_k(P, k);
+  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 6 : 3;
   std::vector<lp_tuning> cand;
   const int64_t c0 = P->plan.min_chunk_rows;
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
     if (fused_ok) {
-      for (int lk = 2; lk <= 6; ++lk)
+      for (int lk = 2; lk <= lk_max; ++lk)
         for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, 0});
     } else {
       cand.push_back({(int32_t)sizeof(lp_tuning), 1, cr, 0, 0});

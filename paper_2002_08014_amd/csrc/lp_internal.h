@@ -27,7 +27,7 @@ struct WorkItem {
 };
 
 // Which local-multiply implementation a problem uses.
-enum class LocalPath : int { TwoPass = 0, Mfma32 = 1 };
+enum class LocalPath : int { TwoPass = 0, Mfma32 = 1, MfmaBf16 = 2 };
 
 struct Layout {
   // byte offsets into the workspace
@@ -118,6 +118,13 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
 // Fused single-pass matrix-core kernel: FP32 A, k = 16, d in {256, 512, 768, 1024}.
 bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k);
 hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t lda, int k,
+                                        const void* Zw, int64_t z_stride, void* part,
+                                        const WorkItem* items, hipStream_t s);
+
+// Fused single-pass matrix-core kernel: BF16 A, k in {16, 32}, d in {512, 1024,
+// 1536, 2048}, rows 16-byte aligned (BF16 operands, FP32 accumulation).
+bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A);
+hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
                                         const WorkItem* items, hipStream_t s);
 
