@@ -1,0 +1,256 @@
+// Two-pass local multiply on FP32 matrix cores, for the shapes the fused
+// kernels do not cover (large d, k up to 64, FP32 or BF16 A):
+//   pass 1  t = A_rows Z_i              (per 128-row block of a work item)
+//   pass 2  part = A_rows^T t           (per 128-column block of a work item)
+// (Eq. (power_yi) without 1/s_i; the per-item partials are reduced per
+// partition in FP64 afterwards.)  A is read twice; at k = 64 the two products
+// cost 4 n d k flops against 2 n d b bytes, so FP32 matrix-core throughput,
+// not HBM, bounds this path.
+//
+// Both kernels: 256 threads (4 waves), a 128 x (16 NT) output block per
+// workgroup, K staged through LDS 32 at a time in two buffers (the next slice
+// is fetched into registers while the current one is multiplied), operands
+// read from LDS one element per lane in the v_mfma_f32_16x16x4f32 layouts
+// (A: lane l holds [l%16][l/16]; B: [l/16][l%16]; D: rows 4(l/16)+r, col l%16).
+// Products are exact in FP32; accumulation is FP32 (BF16 A is widened exactly).
+#include "lp_internal.h"
+
+namespace lp {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 128;   // output rows (pass 1) or columns (pass 2) per workgroup
+constexpr int kBK = 32;    // contraction slice staged per step
+
+template <typename TA>
+__device__ inline f4 load4(const TA* p);
+template <>
+__device__ inline f4 load4<float>(const float* p) {
+  return *(const f4*)p;
+}
+template <>
+__device__ inline f4 load4<__hip_bfloat16>(const __hip_bfloat16* p) {
+  const uint2 v = *(const uint2*)p;
+  return f4{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+            __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u)};
+}
+
+// pass 1: t[row][n] = sum_c A[row][c] Z[c][n]; grid (items, ceil(max item rows / 128))
+template <typename TA, int NT>
+__global__ void __launch_bounds__(256)
+tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ Zw,
+           int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ t) {
+  constexpr int N = 16 * NT;
+  constexpr int AP = kBK + 4;            // padded A row (floats)
+  constexpr int ZP = N + 4;              // padded Z row
+  constexpr int ZE = (kBK * N) / 256;    // Z elements per thread per slice
+  __shared__ float As[2][kBM * AP];
+  __shared__ float Zs[2][kBK * ZP];
+  const WorkItem it = items[blockIdx.x];
+  const int64_t r0 = (int64_t)blockIdx.y * kBM;
+  if (r0 >= it.rows) return;
+  const int rows = (int)min<int64_t>(kBM, it.rows - r0);
+  const TA* Ab = A + (it.row0 + r0) * lda;
+  const float* Z = Zw + (int64_t)it.part * z_stride;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, i = lane & 15;
+
+  // staging: A slice 128 x 32 as 4 groups of 4 elements per thread (row tid/8 + 32j, cols 4(tid%8)..)
+  f4 pa[4];
+  float pz[ZE];
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tid / 8 + 32 * j;
+      const int64_t c = c0 + 4 * (tid % 8);
+      pa[j] = (r < rows && c < d) ? load4<TA>(Ab + (int64_t)r * lda + c) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < ZE; ++j) {
+      const int e = tid + 256 * j;
+      const int kk = e / N, n = e % N;
+      const int64_t c = c0 + kk;
+      pz[j] = (c < d && n < k) ? Z[c * k + n] : 0.f;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(f4*)&As[b][(tid / 8 + 32 * j) * AP + 4 * (tid % 8)] = pa[j];
+#pragma unroll
+    for (int j = 0; j < ZE; ++j) {
+      const int e = tid + 256 * j;
+      Zs[b][(e / N) * ZP + e % N] = pz[j];
+    }
+  };
+
+  f4 acc[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int nsl = (int)((d + kBK - 1) / kBK);
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int s = 0; s < nsl; ++s) {
+    const int b = s & 1;
+    if (s + 1 < nsl) fetch((int64_t)(s + 1) * kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK / 4; ++kk) {
+      float a[2], z[NT];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) a[mt] = As[b][(32 * w + 16 * mt + i) * AP + 4 * kk + g];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) z[nt] = Zs[b][(4 * kk + g) * ZP + 16 * nt + i];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], z[nt], acc[mt][nt], 0, 0, 0);
+    }
+    if (s + 1 < nsl) stash(b ^ 1);
+    __syncthreads();
+  }
+  float* tb = t + (it.row0 + r0) * k;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 32 * w + 16 * mt + 4 * g + r;
+        const int n = 16 * nt + i;
+        if (row < rows && n < k) tb[(int64_t)row * k + n] = acc[mt][nt][r];
+      }
+}
+
+// pass 2: part[slot][c][n] = sum_{rows of item} A[row][c] t[row][n]; grid (items, ceil(d / 128))
+template <typename TA, int NT>
+__global__ void __launch_bounds__(256)
+ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ t,
+           const WorkItem* __restrict__ items, float* __restrict__ part) {
+  constexpr int N = 16 * NT;
+  constexpr int AP = kBM + 4;            // padded A slice row (floats)
+  constexpr int TP = N + 4;
+  constexpr int TE = (kBK * N) / 256;
+  __shared__ float As[2][kBK * AP];
+  __shared__ float Ts[2][kBK * TP];
+  const WorkItem it = items[blockIdx.x];
+  const int64_t c0 = (int64_t)blockIdx.y * kBM;
+  const int rows = (int)it.rows;
+  const TA* Ab = A + it.row0 * lda + c0;
+  const float* tb = t + it.row0 * k;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, i = lane & 15;
+
+  // staging: A slice 32 rows x 128 columns, thread -> row tid/32 + 8j, cols 4(tid%32)..
+  f4 pa[4];
+  float pt[TE];
+  auto fetch = [&](int rs) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rs + tid / 32 + 8 * j;
+      const int64_t c = c0 + 4 * (tid % 32);
+      pa[j] = (r < rows && c < d) ? load4<TA>(Ab + (int64_t)r * lda + 4 * (tid % 32))
+                                  : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < TE; ++j) {
+      const int e = tid + 256 * j;
+      const int rr = e / N, n = e % N;
+      pt[j] = (rs + rr < rows && n < k) ? tb[(int64_t)(rs + rr) * k + n] : 0.f;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(f4*)&As[b][(tid / 32 + 8 * j) * AP + 4 * (tid % 32)] = pa[j];
+#pragma unroll
+    for (int j = 0; j < TE; ++j) {
+      const int e = tid + 256 * j;
+      Ts[b][(e / N) * TP + e % N] = pt[j];
+    }
+  };
+
+  f4 acc[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int nsl = (rows + kBK - 1) / kBK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int s = 0; s < nsl; ++s) {
+    const int b = s & 1;
+    if (s + 1 < nsl) fetch((s + 1) * kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK / 4; ++kk) {
+      float a[2], y[NT];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) a[mt] = As[b][(4 * kk + g) * AP + 32 * w + 16 * mt + i];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) y[nt] = Ts[b][(4 * kk + g) * TP + 16 * nt + i];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], y[nt], acc[mt][nt], 0, 0, 0);
+    }
+    if (s + 1 < nsl) stash(b ^ 1);
+    __syncthreads();
+  }
+  float* o = part + (int64_t)it.slot * d * k;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t c = c0 + 32 * w + 16 * mt + 4 * g + r;
+        const int n = 16 * nt + i;
+        if (c < d && n < k) o[c * k + n] = acc[mt][nt][r];
+      }
+}
+
+template <typename TA, int NT>
+hipError_t gemm_pair(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
+                     int64_t z_stride, void* tbuf, void* part, const WorkItem* items,
+                     hipStream_t s) {
+  const int nitems = (int)P.items.size();
+  dim3 g1(nitems, (unsigned)((P.chunk_rows + kBM - 1) / kBM));
+  tmm_kernel<TA, NT><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)Zw, z_stride, items,
+                                        (float*)tbuf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 g2(nitems, (unsigned)((P.d + kBM - 1) / kBM));
+  ymm_kernel<TA, NT><<<g2, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)tbuf, items,
+                                        (float*)part);
+  return hipGetLastError();
+}
+
+template <typename TA>
+hipError_t gemm_k(const Plan& P, const void* A, int64_t lda, int k, const void* Zw, int64_t z_stride,
+                  void* tbuf, void* part, const WorkItem* items, hipStream_t s) {
+  if (k <= 16) return gemm_pair<TA, 1>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+  if (k <= 32) return gemm_pair<TA, 2>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+  if (k <= 48) return gemm_pair<TA, 3>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+  return gemm_pair<TA, 4>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+}
+
+}  // namespace
+
+bool gemm_eligible(lp_dtype dtype, int64_t d, int64_t lda, const void* A) {
+  const uintptr_t align = dtype == LP_F32 ? 16 : 8;
+  return (dtype == LP_F32 || dtype == LP_BF16) && d % 4 == 0 && lda % 4 == 0 &&
+         ((uintptr_t)A % align) == 0;
+}
+
+hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
+                                      const void* Zw, int64_t z_stride, void* tbuf, void* part,
+                                      const WorkItem* items, hipStream_t s) {
+  if (P.dtype == LP_F32) return gemm_k<float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+  return gemm_k<__hip_bfloat16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+}
+
+}  // namespace lp

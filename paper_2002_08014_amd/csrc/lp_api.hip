@@ -145,6 +145,8 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
     return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, s);
   if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A))
     return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, s);
+  if (gemm_eligible(P.dtype, P.d, lda, A))
+    return launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
 }
 

@@ -128,6 +128,13 @@ hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t ld
                                         const void* Zw, int64_t z_stride, void* part,
                                         const WorkItem* items, hipStream_t s);
 
+// Two-pass form on FP32 matrix cores (t = A Z, then A^T t): FP32 or BF16 A,
+// d % 4 == 0, any k <= 64.
+bool gemm_eligible(lp_dtype dtype, int64_t d, int64_t lda, const void* A);
+hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
+                                      const void* Zw, int64_t z_stride, void* tbuf, void* part,
+                                      const WorkItem* items, hipStream_t s);
+
 hipError_t launch_local_multiply_twopass(const Plan& P, const void* A, int64_t lda, int k,
                                          const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                          const WorkItem* items, hipStream_t s);
