@@ -1,20 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark: LocalPower local-iteration throughput on one MI355X.
 
-Workload (the FP32 fused-path configuration): A is 262144 x 1024 FP32,
+Default workload (the FP32 fused-path configuration): A is 262144 x 1024 FP32,
 low-rank-plus-noise with a spectral gap sigma_16/sigma_17 = 1.2, k = 16,
 m = 32 equal partitions, p = 4, T = 50 rounds, sign-fixing.  One step is one
 full lp_run (50 rounds = 200 local iterations on every partition, with the
 local orthonormalisations, alignments, aggregations and global orths).
 
-value  = algorithmic bytes of A streamed per step (200 * n * d * 4) / step time.
-roofline.achieved = n * d * 4 bytes / average duration of one local-multiply
-launch (HIP events around each launch on the library's stream, inside the
-timed steps); peak = the published 8 TB/s.  The library's autotuner picks the
-local-multiply variant before the timed region; the measured read and copy
-bandwidth of simple streaming kernels is reported beside the roofline.
+Other workloads (--workload): bf16-1048576x2048 (Gaussian rows with a power-law
+covariance stored BF16, k = 32, m = 64, p = 8, 4, 2, 1 for 10 rounds each, OPT)
+and fp32-uneven-500000x4096 (k = 64, m = 100 lognormal partition sizes, p = 4,
+T = 30, OPT).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+value  = algorithmic bytes of A streamed per step (local iterations * n * d * b)
+         / step time.
+roofline.achieved = n * d * b bytes (HBM-bound kernels) or 4 n d k flops
+(the matrix-core-bound two-pass kernel) / average duration of one local
+multiply (HIP events around each launch on the library's stream, inside the
+timed steps); peak = the published 8 TB/s or 157.3 TFLOP/s (FP32 matrix).
+The library's autotuner picks the local-multiply variant before the timed
+region; the measured read and copy bandwidth of simple streaming kernels is
+reported beside the roofline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 
 import argparse
@@ -32,36 +40,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "local-iter GB/s (% HBM peak); rounds to sinθ≤1e-6; jobs/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "local_multiply_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2002_08014_amd", "csrc", f)
-                  for f in ("k_local.hip", "k_mfma.hip")]
+FP32_MATRIX_PEAK_TFS = 157.3
+CSRC = os.path.join(ROOT, "paper_2002_08014_amd", "csrc")
+
+# workload name -> generator, local-multiply sources (for the counter-file hash),
+# counter summary file, bound of the local multiply
+WORKLOADS = {
+    "fp32-262144x1024": dict(gen="make_fp32_262144x1024", sources=("k_local.hip", "k_mfma.hip"),
+                             traffic="local_multiply_traffic.json", bound="hbm"),
+    "bf16-1048576x2048": dict(gen="make_bf16_1048576x2048", sources=("k_mfma_bf16.hip",),
+                              traffic="local_multiply_bf16_traffic.json", bound="hbm"),
+    "fp32-uneven-500000x4096": dict(gen="make_fp32_uneven_500000x4096", sources=("k_gemm.hip",),
+                                    traffic="local_multiply_gemm_traffic.json", bound="mfma"),
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def kernel_hash(sources):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        if os.path.exists(f):
-            h.update(open(f, "rb").read())
+    for f in sources:
+        path = os.path.join(CSRC, f)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(spec):
     """HBM bytes per local-multiply launch from the committed counter summary,
     or None when the kernel sources changed since the counters were taken."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(os.path.join(ROOT, "profiles", spec["traffic"])))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(spec["sources"]):
         return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(A_dev, offsets, k, Y0, budget_s=12.0):
+def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle on a bounded sample: the first 4 partitions, one round of
     p = 4 local iterations repeated until the time budget is used."""
     import oracle
@@ -71,21 +90,22 @@ def cpu_baseline(A_dev, offsets, k, Y0, budget_s=12.0):
     except Exception:
         cores = os.cpu_count()
     parts = 4
-    rows = int(offsets[parts])
-    A = A_dev[:rows].to("cpu").to(torch.float64).numpy()
-    sub = np.asarray(offsets[:parts + 1])
+    rows = int(w.offsets[parts])
+    A = w.A[:rows].to("cpu").to(torch.float64).numpy()
+    sub = np.asarray(w.offsets[:parts + 1])
     d = A.shape[1]
+    b = w.A.element_size()
     iters = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        oracle.localpower(A, sub, k, [4], "sign", Y0)
+        oracle.localpower(A, sub, w.k, [4], "sign", w.Y0)
         iters += 4
     el = time.perf_counter() - t0
-    gbs = iters * rows * d * 4 / el / 1e9
+    gbs = iters * rows * d * b / el / 1e9
     return {"value": gbs, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {parts} of 32 partitions ({rows}x{d} upcast to FP64), "
-                      f"{iters // 4} rounds of p=4 sign-fixing in {el:.1f} s; bytes counted as FP32 "
-                      f"storage like the GPU figure"}
+            "sample": f"first {parts} of {w.m} partitions ({rows}x{d} upcast to FP64), "
+                      f"{iters // 4} rounds of p=4 sign-fixing in {el:.1f} s; bytes counted at the "
+                      f"stored width ({b} B) like the GPU figure"}
 
 
 def rounds_to(hist, thresholds=(1e-1, 1e-2, 1e-3, 1e-6)):
@@ -114,8 +134,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rounds", type=int, default=50)
-    ap.add_argument("--mode", default="sign", choices=["sign", "opt", "vanilla"])
+    ap.add_argument("--workload", default="fp32-262144x1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--rounds", type=int, default=0, help="override the workload's round count")
+    ap.add_argument("--mode", default=None, choices=["sign", "opt", "vanilla"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
     args = ap.parse_args()
@@ -126,10 +147,15 @@ def main():
     import synth
     import paper_2002_08014_amd as lp
 
+    spec = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log("generating A 262144x1024 fp32 on the GPU")
-    w = synth.make_c2(device=dev, mode=args.mode, rounds=args.rounds)
+    log(f"generating {args.workload} on the GPU")
+    w = getattr(synth, spec["gen"])(device=dev)
+    if args.mode:
+        w.mode = args.mode
+    if args.rounds:
+        w.p_sched = (list(w.p_sched) * args.rounds)[:args.rounds]
     n, d, k = w.n, w.d, w.k
     torch.cuda.synchronize()
     P = lp.lp_create(w.A, w.offsets, k)
@@ -141,17 +167,17 @@ def main():
     copy_gbs = lp.lp_copy_probe(buf[1 << 30:], buf[:1 << 30], 5)
     del buf
     torch.cuda.synchronize()
-    sched = w.p_sched
+    sched = list(w.p_sched)
     iters_per_step = int(sum(sched))
     log(f"warmup x{args.warmup}")
     for _ in range(args.warmup):
-        lp.lp_run(P, k, sched, args.mode, w.Y0, time_local=True)
+        lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=True)
     torch.cuda.synchronize()
     log(f"timed x{args.steps}")
     ms_local, launches, graph_rounds = 0.0, 0, 0
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = lp.lp_run(P, k, sched, args.mode, w.Y0, time_local=True)
+        r = lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=True)
         ms_local += r["stats"]["ms_local"]
         launches += r["stats"]["local_launches"]
         graph_rounds += r["stats"]["graph_rounds"]
@@ -159,10 +185,22 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     bytes_iter = n * d * w.A.element_size()
+    flops_iter = 4.0 * n * d * k
     value = args.steps * iters_per_step * bytes_iter / el / 1e9
     k1_ms = ms_local / max(launches, 1)
-    achieved = bytes_iter / (k1_ms / 1e3) / 1e9
-    traffic = traffic_per_launch()
+    if spec["bound"] == "hbm":
+        achieved = bytes_iter / (k1_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    else:
+        achieved = flops_iter / (k1_ms / 1e3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MATRIX_PEAK_TFS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MATRIX_PEAK_TFS, 4),
+                "hbm_gbs": round(bytes_iter / (k1_ms / 1e3) / 1e9, 2)}
+    roof.update({"traffic": traffic_per_launch(spec), "kernel_ms": round(k1_ms, 5), "launches": launches,
+                 "measured_read_gbs": round(read_gbs, 1), "measured_copy_gbs": round(copy_gbs, 1)})
+    dtype = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float64: "f64"}[w.A.dtype]
+    ps = sorted(set(sched), reverse=True)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -174,25 +212,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"localpower fp32 A {n}x{d}, k={k}, m={w.m} equal partitions, "
-                               f"p=4, T={len(sched)} rounds, {args.mode} alignment",
-                   "n": n, "d": d, "k": k, "m": w.m, "p": 4, "rounds": len(sched),
-                   "local_iters_per_step": iters_per_step, "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "config": {"workload": f"localpower {dtype} A {n}x{d}, k={k}, m={w.m} "
+                               f"{'lognormal' if args.workload.startswith('fp32-uneven') else 'equal'} "
+                               f"partitions, p in {ps}, T={len(sched)} rounds, {w.mode} alignment",
+                   "n": n, "d": d, "k": k, "m": w.m, "p_sched": sched if len(ps) > 1 else ps[0],
+                   "rounds": len(sched), "local_iters_per_step": iters_per_step,
+                   "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
                    "tuning": tuning, "graph_rounds": graph_rounds,
                    "rounds_total": args.steps * len(sched)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel_ms": round(k1_ms, 5), "launches": launches,
-                     "measured_read_gbs": round(read_gbs, 1), "measured_copy_gbs": round(copy_gbs, 1)},
+        "roofline": roof,
     }
-    if not args.no_convergence:
+    if not args.no_convergence and args.workload == "fp32-262144x1024":
         log("convergence (rounds to sin theta thresholds)")
         out["convergence"] = convergence(lp, P, w, k)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
-        out["cpu_baseline"] = cpu_baseline(w.A, w.offsets, k, w.Y0)
+        out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 
 

@@ -10,53 +10,61 @@
 namespace lp {
 namespace {
 
-constexpr int kTile = 64;  // rows staged in LDS per step of the Gram kernel
+// Cross-Gram partial out[i][j] = sum_r Xs[r][i] Ws[r][j] over `rows` rows of the
+// LDS blocks Xs, Ws (row stride k <= 16 KC); thread (ty, tx) = (tid / 16, tid % 16)
+// owns the entries (ty + 16a, tx + 16c), a, c < KC.  Needs kBlock threads.
+template <int KC>
+__device__ void gram_tile(const double* Xs, const double* Ws, int rows, int k, double* out) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double acc[KC][KC];
+#pragma unroll
+  for (int a = 0; a < KC; ++a)
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[a][c] = 0.0;
+  for (int r = 0; r < rows; ++r) {
+    double xi[KC], wj[KC];
+#pragma unroll
+    for (int a = 0; a < KC; ++a) xi[a] = (ty + 16 * a < k) ? Xs[r * k + ty + 16 * a] : 0.0;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) wj[c] = (tx + 16 * c < k) ? Ws[r * k + tx + 16 * c] : 0.0;
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc[a][c] = fma(xi[a], wj[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int a = 0; a < KC; ++a)
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (ty + 16 * a < k && tx + 16 * c < k) out[(ty + 16 * a) * k + tx + 16 * c] = acc[a][c];
+}
+
+// 16-column blocks needed for k columns
+constexpr int kc_of(int km) { return (km + 15) / 16; }
 
 // ---------------------------------------------------------------------------
 // G_b(chunk) = X_b[rows]^T W_b[rows]  (k x k partial, chunk of kGramRows rows)
 // grid: (nchunks, batch), block kBlock
 // ---------------------------------------------------------------------------
+template <int KC>
 __global__ void __launch_bounds__(kBlock)
 cross_gram_kernel(int64_t d, int k, const double* __restrict__ X, int64_t x_stride,
                   const double* __restrict__ W, int64_t w_stride, double* __restrict__ out) {
-  __shared__ double xs[kTile * kMaxK];
-  __shared__ double ws[kTile * kMaxK];
+  __shared__ double xs[kGramRows * kMaxK];
+  __shared__ double ws[kGramRows * kMaxK];
   const int b = blockIdx.y;
   const int c = blockIdx.x;
   const int nchunks = gridDim.x;
-  const int64_t r_begin = (int64_t)c * kGramRows;
-  const int64_t r_end = min(d, r_begin + kGramRows);
-  const double* Xb = X + b * x_stride;
-  const double* Wb = W + b * w_stride;
-  const int kk = k * k;
-  double acc[(kMaxK * kMaxK) / kBlock];
-#pragma unroll
-  for (int e = 0; e < (kMaxK * kMaxK) / kBlock; ++e) acc[e] = 0.0;
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kTile) {
-    const int rows = (int)min<int64_t>(kTile, r_end - r0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < rows * k; e += kBlock) {
-      xs[e] = Xb[r0 * k + e];
-      ws[e] = Wb[r0 * k + e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < (kMaxK * kMaxK) / kBlock; ++q) {
-      const int e = threadIdx.x + q * kBlock;
-      if (e < kk) {
-        const int i = e / k, j = e - (e / k) * k;
-        double s = acc[q];
-        for (int r = 0; r < rows; ++r) s = fma(xs[r * k + i], ws[r * k + j], s);
-        acc[q] = s;
-      }
-    }
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  const double* Xb = X + b * x_stride + r0 * k;
+  const double* Wb = W + b * w_stride + r0 * k;
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
+    xs[e] = Xb[e];
+    ws[e] = Wb[e];
   }
-  double* o = out + ((int64_t)b * nchunks + c) * kk;
-#pragma unroll
-  for (int q = 0; q < (kMaxK * kMaxK) / kBlock; ++q) {
-    const int e = threadIdx.x + q * kBlock;
-    if (e < kk) o[e] = acc[q];
-  }
+  __syncthreads();
+  gram_tile<KC>(xs, ws, rows, k, out + ((int64_t)b * nchunks + c) * k * k);
 }
 
 // sum_{q < n} p[q * stride] with eight interleaved accumulators combined in a
@@ -81,60 +89,15 @@ __device__ void sum_partials(const double* __restrict__ part, int b, int nchunks
     G[e] = sum_strided(part + (int64_t)b * nchunks * kk + e, kk, nchunks);
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky G = R^T R (R upper, positive diagonal) and R^{-1}; grid (batch)
-// ---------------------------------------------------------------------------
+// grid (ceil(kk / kBlock), batch): out[b][e] = sum of the nch partials of entry e
+// of matrix b (fixed order), one thread per entry.
 __global__ void __launch_bounds__(kBlock)
-chol_inv_kernel(int nchunks, int k, const double* __restrict__ part, double* __restrict__ rinv,
-                int32_t* __restrict__ flags) {
-  __shared__ double R[kMaxK * kMaxK];
-  __shared__ double X[kMaxK * kMaxK];
-  __shared__ int bad;
-  const int b = blockIdx.x;
-  if (threadIdx.x == 0) bad = 0;
-  sum_partials(part, b, nchunks, k, R);
-  __syncthreads();
-  // left-looking Cholesky, row j of R at step j
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
-      double djj = R[j * k + j];
-      for (int l = 0; l < j; ++l) djj -= R[l * k + j] * R[l * k + j];
-      if (!(djj > 0.0) || !isfinite(djj)) {
-        bad = 1;
-        djj = 1.0;
-      }
-      R[j * k + j] = sqrt(djj);
-    }
-    __syncthreads();
-    const double rjj = R[j * k + j];
-    for (int c = j + 1 + threadIdx.x; c < k; c += blockDim.x) {
-      double v = R[j * k + c];
-      for (int l = 0; l < j; ++l) v -= R[l * k + j] * R[l * k + c];
-      R[j * k + c] = v / rjj;
-    }
-    __syncthreads();
-  }
-  // inverse of the upper triangular R, one column per thread (back substitution)
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    X[c * k + c] = 1.0 / R[c * k + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int l = i + 1; l <= c; ++l) s += R[i * k + l] * X[l * k + c];
-      X[i * k + c] = -s / R[i * k + i];
-    }
-  }
-  __syncthreads();
-  double* out = rinv + (int64_t)b * k * k;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    const int i = e / k, c = e - (e / k) * k;
-    double v = (i <= c) ? X[e] : 0.0;
-    if (bad) v = (i == c) ? 1.0 : 0.0;
-    out[e] = v;
-  }
-  if (threadIdx.x == 0 && flags != nullptr && bad) flags[b] = 1;
+sum_gram_kernel(int nch, int kk, const double* __restrict__ part, double* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= kk) return;
+  out[(int64_t)b * kk + e] = sum_strided(part + (int64_t)b * nch * kk + e, kk, nch);
 }
-
-
 
 __device__ inline double rdlane(double v, int l) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -201,57 +164,7 @@ __device__ void chol_inv_wave(const double* G, double* Ri, int k, int* bad) {
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky of the k x k LDS matrix R (in place: upper R with R^T R = G, positive
-// diagonal) and the inverse of R into X.  All threads of the block take part.
-// *bad is set on breakdown (non-positive or non-finite pivot), and then R^{-1}
-// is replaced by the identity so that downstream values stay finite.
-// ---------------------------------------------------------------------------
-__device__ void chol_inv_block(double* R, double* X, int k, int* bad) {
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
-      double djj = R[j * k + j];
-      for (int l = 0; l < j; ++l) djj -= R[l * k + j] * R[l * k + j];
-      if (!(djj > 0.0) || !isfinite(djj)) {
-        *bad = 1;
-        djj = 1.0;
-      }
-      R[j * k + j] = sqrt(djj);
-    }
-    __syncthreads();
-    const double rjj = R[j * k + j];
-    for (int c = j + 1 + threadIdx.x; c < k; c += blockDim.x) {
-      double v = R[j * k + c];
-      for (int l = 0; l < j; ++l) v -= R[l * k + j] * R[l * k + c];
-      R[j * k + c] = v / rjj;
-    }
-    __syncthreads();
-  }
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    for (int i = c + 1; i < k; ++i) X[i * k + c] = 0.0;
-    X[c * k + c] = 1.0 / R[c * k + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int l = i + 1; l <= c; ++l) s += R[i * k + l] * X[l * k + c];
-      X[i * k + c] = -s / R[i * k + i];
-    }
-  }
-  __syncthreads();
-  if (*bad)
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) X[e] = (e / k == e % k) ? 1.0 : 0.0;
-  __syncthreads();
-}
 
-// Gram partial of the `rows` x k LDS block Qs into out[k*k] (k*k <= KM*KM).
-template <int KM>
-__device__ void gram_block(const double* Qs, int rows, int k, double* out) {
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    const int i = e / k, j = e - (e / k) * k;
-    double s = 0.0;
-    for (int r = 0; r < rows; ++r) s = fma(Qs[r * k + i], Qs[r * k + j], s);
-    out[e] = s;
-  }
-}
 
 // grid (nch, m): Y_i rows of chunk c = sum of the partition's partial slots, and their Gram.
 template <typename TC, int KM>
@@ -271,7 +184,7 @@ reduce_gram_kernel(int64_t d, int k, const TC* __restrict__ part,
     ys[e] = v;
   }
   __syncthreads();
-  gram_block<KM>(ys, rows, k, gram + ((int64_t)b * nch + c) * k * k);
+  gram_tile<kc_of(KM)>(ys, ys, rows, k, gram + ((int64_t)b * nch + c) * k * k);
 }
 
 // grid (nch): Y rows = scale * sum_i Yi rows, and their Gram.
@@ -290,42 +203,9 @@ aggregate_gram_kernel(int m, int64_t d, int k, const double* __restrict__ Yi, do
     ys[e] = v;
   }
   __syncthreads();
-  gram_block<KM>(ys, rows, k, gram + (int64_t)c * k * k);
+  gram_tile<kc_of(KM)>(ys, ys, rows, k, gram + (int64_t)c * k * k);
 }
 
-// grid (nch, batch): one CholeskyQR pass for row chunk c of matrix b.
-template <typename TW, int KM>
-__global__ void __launch_bounds__(kBlock)
-chol_apply_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ gin,
-                  double* __restrict__ Q, TW* __restrict__ zw, double* __restrict__ gout,
-                  int32_t* __restrict__ flags) {
-  __shared__ double R[KM * KM];
-  __shared__ double Ri[KM * KM];
-  __shared__ double qs[kGramRows * KM];
-  __shared__ int bad;
-  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
-  if (threadIdx.x == 0) bad = 0;
-  sum_partials(gin, b, nch, k, R);
-  __syncthreads();
-  chol_inv_wave<KM>(R, Ri, k, &bad);
-  const int64_t r0 = (int64_t)c * kGramRows;
-  const int rows = (int)min<int64_t>(kGramRows, d - r0);
-  const int64_t base = (int64_t)b * d * k + r0 * k;
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
-    const int rr = e / k, j = e - (e / k) * k;
-    const double* xr = X + base + (int64_t)rr * k;
-    double v = 0.0;
-    for (int l = 0; l <= j; ++l) v = fma(xr[l], Ri[l * k + j], v);
-    Q[base + e] = v;
-    if (zw != nullptr) zw[base + e] = (TW)v;
-    qs[e] = v;
-  }
-  if (gout != nullptr) {
-    __syncthreads();
-    gram_block<KM>(qs, rows, k, gout + ((int64_t)b * nch + c) * k * k);
-  }
-  if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
-}
 
 
 // grid (batch), block kBlock: R^{-1} of chol(sum of the Gram partials) for
@@ -346,32 +226,62 @@ chol_inv_wave_kernel(int nch, int k, const double* __restrict__ gin, double* __r
   if (threadIdx.x == 0 && bad && flags != nullptr) flags[b] = 1;
 }
 
-// grid (nch, batch): Q = X R^{-1} for row chunk c of matrix b (R^{-1} upper, from rinv),
-// optional working copy and Gram partials of Q.
-template <typename TW, int KM>
+// grid (ceil(d / 64), batch): Q = X R^{-1} for the 64-row chunk c of matrix b
+// (R^{-1} upper triangular, from rinv), the optional working copy, and the
+// optional Gram partial of the chunk's rows of Q (partial index b * gridDim.x + c).
+// X and R^{-1} staged in LDS; thread (ty, tx) computes rows ty + 16a and
+// columns tx + 16c of the chunk.
+template <typename TW, int KC>
 __global__ void __launch_bounds__(kBlock)
 apply_gram_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ rinv,
                   double* __restrict__ Q, TW* __restrict__ zw, double* __restrict__ gout) {
-  __shared__ double Ri[KM * KM];
-  __shared__ double qs[kGramRows * KM];
+  __shared__ double Ri[kMaxK * kMaxK];
+  __shared__ double Xs[kGramRows * kMaxK];
   const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
-  for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rinv[(int64_t)b * k * k + e];
-  __syncthreads();
   const int64_t r0 = (int64_t)c * kGramRows;
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const int64_t base = (int64_t)b * d * k + r0 * k;
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
-    const int rr = e / k, j = e - (e / k) * k;
-    const double* xr = X + base + (int64_t)rr * k;
-    double v = 0.0;
-    for (int l = 0; l <= j; ++l) v = fma(xr[l], Ri[l * k + j], v);
-    Q[base + e] = v;
-    if (zw != nullptr) zw[base + e] = (TW)v;
-    qs[e] = v;
+  for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rinv[(int64_t)b * k * k + e];
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = X[base + e];
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double acc[4][KC];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) acc[a][cc] = 0.0;
+  for (int l = 0; l < k; ++l) {
+    double xv[4], sv[KC];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xv[a] = (ty + 16 * a < rows) ? Xs[(ty + 16 * a) * k + l] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) {
+      const int j = tx + 16 * cc;
+      sv[cc] = (j < k && l <= j) ? Ri[l * k + j] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int cc = 0; cc < KC; ++cc) acc[a][cc] = fma(xv[a], sv[cc], acc[a][cc]);
+  }
+  __syncthreads();   // every thread has read Xs; it now holds the chunk of Q
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = ty + 16 * a;
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) {
+      const int j = tx + 16 * cc;
+      if (r < rows && j < k) {
+        const double v = acc[a][cc];
+        Q[base + (int64_t)r * k + j] = v;
+        if (zw != nullptr) zw[base + (int64_t)r * k + j] = (TW)v;
+        Xs[r * k + j] = v;
+      }
+    }
   }
   if (gout != nullptr) {
     __syncthreads();
-    gram_block<KM>(qs, rows, k, gout + ((int64_t)b * nch + c) * k * k);
+    gram_tile<KC>(Xs, Xs, rows, k, gout + ((int64_t)b * nch + c) * k * k);
   }
 }
 
@@ -425,11 +335,12 @@ struct ChunkRows {
   static constexpr int value = (32768 / 8) / KM;  // 256 for k <= 16, 128 for 32, 64 for 64
 };
 
-// grid (ceil(d / RC), batch): one CholeskyQR pass for a row chunk: sum the nch_in
-// Gram partials of matrix b, Cholesky-factor them (every workgroup redundantly,
-// in one wavefront), forward-substitute Q_row = X_row R^{-1} (one thread per
-// row), and optionally write the working copy and the Gram partial of the
-// chunk's rows (chunk = RC rows, partial index b * gridDim.x + c).
+// grid (ceil(d / RC), batch): one CholeskyQR pass for a row chunk of matrix b
+// (small k): sum the nch_in Gram partials and factor them in every workgroup
+// (one wavefront; cheaper than a separate launch at this size), forward-
+// substitute Q_row = X_row R^{-1} (one thread per row), and optionally write
+// the working copy and the Gram partial of the chunk's rows (chunk = RC rows,
+// partial index b * gridDim.x + c).
 template <typename TW, int KM>
 __global__ void __launch_bounds__(kBlock)
 chol_solve_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
@@ -446,6 +357,7 @@ chol_solve_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
   sum_partials(gin, b, nch_in, k, G);
   __syncthreads();
   chol_wave<KM>(G, R, rdi, k, &bad);
+  if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
   const int64_t r0 = (int64_t)c * RC;
   const int rows = (int)min<int64_t>(RC, d - r0);
   for (int rr = threadIdx.x; rr < rows; rr += kBlock) {
@@ -472,9 +384,8 @@ chol_solve_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
   }
   if (gout != nullptr) {
     __syncthreads();
-    gram_block<KM>(qs, rows, k, gout + ((int64_t)b * nch_out + c) * k * k);
+    gram_tile<kc_of(KM)>(qs, qs, rows, k, gout + ((int64_t)b * nch_out + c) * k * k);
   }
-  if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
 }
 
 // grid (nch, batch): partial column dots of chunk c: part[(b*nch + c)*k + j].
@@ -527,27 +438,58 @@ sign_apply_kernel(int64_t d, int k, const double* __restrict__ part, double* __r
 }
 
 // ---------------------------------------------------------------------------
-// Q_b = X_b S_b; grid (ceil(d*k / kBlock), batch)
+// Q_b = X_b S_b (S upper triangular when `upper`); grid (ceil(d / 64), batch)
 // ---------------------------------------------------------------------------
 template <typename TW>
 __global__ void __launch_bounds__(kBlock)
 right_mult_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ S,
                   int64_t s_stride, int upper, double* __restrict__ Q, TW* __restrict__ zw) {
+  // 64-row tile of X and S staged in LDS; thread (ty, tx) = (tid / 16, tid % 16)
+  // computes rows ty + 16a and columns tx + 16c of the tile (a, c < 4)
+  constexpr int TR = 64;
   __shared__ double Ss[kMaxK * kMaxK];
+  __shared__ double Xs[TR * kMaxK];
   const int b = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * TR;
+  const int rows = (int)min<int64_t>(TR, d - r0);
   const double* Sb = S + b * s_stride;
+  const double* Xb = X + (int64_t)b * d * k + r0 * k;
   for (int e = threadIdx.x; e < k * k; e += kBlock) Ss[e] = Sb[e];
+  for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = Xb[e];
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= d * k) return;
-  const int64_t r = e / k;
-  const int j = (int)(e - r * k);
-  const double* xr = X + (int64_t)b * d * k + r * k;
-  const int lend = upper ? j + 1 : k;
-  double s = 0.0;
-  for (int l = 0; l < lend; ++l) s = fma(xr[l], Ss[l * k + j], s);
-  if (Q != nullptr) Q[(int64_t)b * d * k + e] = s;
-  if (zw != nullptr) zw[(int64_t)b * d * k + e] = (TW)s;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  for (int l = 0; l < k; ++l) {
+    double xv[4], sv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xv[a] = (ty + 16 * a < rows) ? Xs[(ty + 16 * a) * k + l] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = tx + 16 * c;
+      sv[c] = (j < k && (!upper || l <= j)) ? Ss[l * k + j] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a], sv[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = ty + 16 * a;
+    if (r >= rows) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = tx + 16 * c;
+      if (j >= k) continue;
+      const int64_t o = (int64_t)b * d * k + (r0 + r) * k + j;
+      if (Q != nullptr) Q[o] = acc[a][c];
+      if (zw != nullptr) zw[o] = (TW)acc[a][c];
+    }
+  }
 }
 
 template <typename TW>
@@ -571,17 +513,6 @@ __global__ void sign_from_gram_kernel(int batch, int nchunks, int k, const doubl
   sgn[t] = (s >= 0.0) ? (int8_t)1 : (int8_t)-1;
 }
 
-template <typename TW>
-__global__ void apply_signs_kernel(int batch, int64_t d, int k, double* __restrict__ X,
-                                   const int8_t* __restrict__ sgn, TW* __restrict__ zw) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)batch * d * k) return;
-  const int64_t b = e / (d * k);
-  const int j = (int)(e % k);
-  const double v = X[e] * (double)sgn[b * k + j];
-  X[e] = v;
-  if (zw != nullptr) zw[e] = (TW)v;
-}
 
 // ---------------------------------------------------------------------------
 // Jacobi helpers (one workgroup, matrices in LDS)
@@ -686,7 +617,7 @@ __device__ void jacobi_sym_lds(double* S, double* V, int k, double* cs, double* 
 // Orthogonal Procrustes O = W1 W2^T of C = W1 S W2^T (one-sided Jacobi); grid (batch)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
-procrustes_kernel(int nchunks, int k, const double* __restrict__ part, double* __restrict__ O,
+procrustes_kernel(int nchunks, int k, const double* part, double* O,
                   int32_t* __restrict__ flags) {
   __shared__ double X[kMaxK * kMaxK];
   __shared__ double V[kMaxK * kMaxK];
@@ -912,20 +843,20 @@ hipError_t sin_slot_address(double** p) {
 hipError_t launch_cross_gram(int batch, int64_t d, int k, const double* X, int64_t x_stride,
                              const double* W, int64_t w_stride, double* gram_part, hipStream_t s) {
   dim3 grid(nblk(d, kGramRows), batch);
-  cross_gram_kernel<<<grid, kBlock, 0, s>>>(d, k, X, x_stride, W, w_stride, gram_part);
+  if (k <= 16)
+    cross_gram_kernel<1><<<grid, kBlock, 0, s>>>(d, k, X, x_stride, W, w_stride, gram_part);
+  else if (k <= 32)
+    cross_gram_kernel<2><<<grid, kBlock, 0, s>>>(d, k, X, x_stride, W, w_stride, gram_part);
+  else
+    cross_gram_kernel<4><<<grid, kBlock, 0, s>>>(d, k, X, x_stride, W, w_stride, gram_part);
   return hipGetLastError();
 }
 
-hipError_t launch_chol_inv(int batch, int nchunks, int k, const double* gram_part, double* rinv,
-                           int32_t* flags, hipStream_t s) {
-  chol_inv_kernel<<<batch, kBlock, 0, s>>>(nchunks, k, gram_part, rinv, flags);
-  return hipGetLastError();
-}
 
 hipError_t launch_right_mult(int batch, int64_t d, int k, const double* X, const double* S,
                              int64_t s_stride, bool upper, double* Q, void* zw, size_t zw_bytes,
                              hipStream_t s) {
-  dim3 grid(nblk(d * k, kBlock), batch);
+  dim3 grid(nblk(d, 64), batch);
   if (zw == nullptr || zw_bytes == 8)
     right_mult_kernel<double><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, upper ? 1 : 0, Q,
                                                        (double*)zw);
@@ -952,21 +883,18 @@ hipError_t launch_sign_from_gram(int batch, int nchunks, int k, const double* gr
   return hipGetLastError();
 }
 
-hipError_t launch_apply_signs(int batch, int64_t d, int k, double* X, const int8_t* sgn, void* zw,
-                              size_t zw_bytes, hipStream_t s) {
-  const int64_t count = (int64_t)batch * d * k;
-  if (zw == nullptr || zw_bytes == 8)
-    apply_signs_kernel<double><<<nblk(count, kBlock), kBlock, 0, s>>>(batch, d, k, X, sgn,
-                                                                     (double*)zw);
-  else
-    apply_signs_kernel<float><<<nblk(count, kBlock), kBlock, 0, s>>>(batch, d, k, X, sgn,
-                                                                    (float*)zw);
-  return hipGetLastError();
-}
 
 hipError_t launch_procrustes(int batch, int nchunks, int k, const double* gram_part, double* O,
                              int32_t* flags, hipStream_t s) {
-  procrustes_kernel<<<batch, kBlock, 0, s>>>(nchunks, k, gram_part, O, flags);
+  if (k > 16 && nchunks > 1) {
+    // sum the partials with a wide launch into O (the kernel reads O[b] in full
+    // before it writes O[b])
+    sum_gram_kernel<<<dim3(nblk((int64_t)k * k, kBlock), batch), kBlock, 0, s>>>(nchunks, k * k,
+                                                                               gram_part, O);
+    procrustes_kernel<<<batch, kBlock, 0, s>>>(1, k, O, O, flags);
+  } else {
+    procrustes_kernel<<<batch, kBlock, 0, s>>>(nchunks, k, gram_part, O, flags);
+  }
   return hipGetLastError();
 }
 
@@ -995,11 +923,15 @@ hipError_t launch_reduce_gram(const Plan& P, int k, const void* part, const int3
                               double* Yi, double* gram, hipStream_t s) {
   dim3 grid(nblk(P.d, kGramRows), P.m);
   if (P.acc_bytes == 8) {
-    if (k <= 16) reduce_gram_kernel<double, 16><<<grid, kBlock, 0, s>>>(P.d, k, (const double*)part, slot_off, Yi, gram);
-    else reduce_gram_kernel<double, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, (const double*)part, slot_off, Yi, gram);
+    const double* pp = (const double*)part;
+    if (k <= 16) reduce_gram_kernel<double, 16><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
+    else if (k <= 32) reduce_gram_kernel<double, 32><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
+    else reduce_gram_kernel<double, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
   } else {
-    if (k <= 16) reduce_gram_kernel<float, 16><<<grid, kBlock, 0, s>>>(P.d, k, (const float*)part, slot_off, Yi, gram);
-    else reduce_gram_kernel<float, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, (const float*)part, slot_off, Yi, gram);
+    const float* pp = (const float*)part;
+    if (k <= 16) reduce_gram_kernel<float, 16><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
+    else if (k <= 32) reduce_gram_kernel<float, 32><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
+    else reduce_gram_kernel<float, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
   }
   return hipGetLastError();
 }
@@ -1008,89 +940,58 @@ hipError_t launch_aggregate_gram(int m, int64_t d, int k, const double* Yi, doub
                                  double* gram, hipStream_t s) {
   dim3 grid(nblk(d, kGramRows));
   if (k <= 16) aggregate_gram_kernel<16><<<grid, kBlock, 0, s>>>(m, d, k, Yi, scale, Y, gram);
+  else if (k <= 32) aggregate_gram_kernel<32><<<grid, kBlock, 0, s>>>(m, d, k, Yi, scale, Y, gram);
   else aggregate_gram_kernel<kMaxK><<<grid, kBlock, 0, s>>>(m, d, k, Yi, scale, Y, gram);
   return hipGetLastError();
 }
 
-template <typename TW>
-static void chol_apply_t(dim3 grid, int64_t d, int k, const double* X, const double* gin, double* Q,
-                         TW* zw, double* gout, int32_t* flags, hipStream_t s) {
-  if (k <= 16)
-    chol_apply_kernel<TW, 16><<<grid, kBlock, 0, s>>>(d, k, X, gin, Q, zw, gout, flags);
-  else if (k <= 32)
-    chol_apply_kernel<TW, 32><<<grid, kBlock, 0, s>>>(d, k, X, gin, Q, zw, gout, flags);
-  else
-    chol_apply_kernel<TW, kMaxK><<<grid, kBlock, 0, s>>>(d, k, X, gin, Q, zw, gout, flags);
-}
-
-hipError_t launch_chol_apply(int batch, int64_t d, int k, const double* X, const double* gram_in,
-                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
-                             int32_t* flags, hipStream_t s) {
-  dim3 grid(nblk(d, kGramRows), batch);
-  if (zw == nullptr || zw_bytes == 8)
-    chol_apply_t<double>(grid, d, k, X, gram_in, Q, (double*)zw, gram_out, flags, s);
-  else
-    chol_apply_t<float>(grid, d, k, X, gram_in, Q, (float*)zw, gram_out, flags, s);
-  return hipGetLastError();
-}
 
 
-hipError_t launch_chol_inv_wave(int batch, int nch, int k, const double* gram, double* rinv,
+
+
+
+
+template <typename TW, int KM>
+static hipError_t chol_solve_km(int batch, int64_t d, int k, int nch_in, const double* X,
+                                const double* gin, double* rfac, double* Q, TW* zw, double* gout,
                                 int32_t* flags, hipStream_t s) {
-  if (k <= 16) chol_inv_wave_kernel<16><<<batch, kBlock, 0, s>>>(nch, k, gram, rinv, flags);
-  else if (k <= 32) chol_inv_wave_kernel<32><<<batch, kBlock, 0, s>>>(nch, k, gram, rinv, flags);
-  else chol_inv_wave_kernel<kMaxK><<<batch, kBlock, 0, s>>>(nch, k, gram, rinv, flags);
-  return hipGetLastError();
-}
-
-template <typename TW>
-static void apply_gram_t(dim3 grid, int64_t d, int k, const double* X, const double* rinv,
-                         double* Q, TW* zw, double* gout, hipStream_t s) {
-  if (k <= 16) apply_gram_kernel<TW, 16><<<grid, kBlock, 0, s>>>(d, k, X, rinv, Q, zw, gout);
-  else if (k <= 32) apply_gram_kernel<TW, 32><<<grid, kBlock, 0, s>>>(d, k, X, rinv, Q, zw, gout);
-  else apply_gram_kernel<TW, kMaxK><<<grid, kBlock, 0, s>>>(d, k, X, rinv, Q, zw, gout);
-}
-
-hipError_t launch_apply_gram(int batch, int64_t d, int k, const double* X, const double* rinv,
-                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
-                             hipStream_t s) {
-  dim3 grid(nblk(d, kGramRows), batch);
-  if (zw == nullptr || zw_bytes == 8)
-    apply_gram_t<double>(grid, d, k, X, rinv, Q, (double*)zw, gram_out, s);
-  else
-    apply_gram_t<float>(grid, d, k, X, rinv, Q, (float*)zw, gram_out, s);
-  return hipGetLastError();
-}
-
-
-template <typename TW>
-static hipError_t chol_solve_t(int batch, int64_t d, int k, int nch_in, const double* X,
-                               const double* gin, double* Q, TW* zw, double* gout, int32_t* flags,
-                               hipStream_t s) {
-  if (k <= 16) {
-    dim3 grid(nblk(d, ChunkRows<16>::value), batch);
-    chol_solve_kernel<TW, 16><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
-  } else if (k <= 32) {
-    dim3 grid(nblk(d, ChunkRows<32>::value), batch);
-    chol_solve_kernel<TW, 32><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
+  if constexpr (KM <= 16) {
+    dim3 grid(nblk(d, ChunkRows<KM>::value), batch);
+    chol_solve_kernel<TW, KM><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
   } else {
-    dim3 grid(nblk(d, ChunkRows<kMaxK>::value), batch);
-    chol_solve_kernel<TW, kMaxK><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
+    // larger k: factor and invert once per matrix, then multiply the 64-row chunks
+    // the Gram partials are summed by a wide launch first (one sum per entry,
+    // all of them in parallel), then factored and inverted once per matrix
+    double* gsum = rfac + (int64_t)batch * k * k;
+    sum_gram_kernel<<<dim3(nblk((int64_t)k * k, kBlock), batch), kBlock, 0, s>>>(nch_in, k * k, gin, gsum);
+    chol_inv_wave_kernel<KM><<<batch, kBlock, 0, s>>>(1, k, gsum, rfac, flags);
+    dim3 g2(nblk(d, kGramRows), batch);
+    apply_gram_kernel<TW, kc_of(KM)><<<g2, kBlock, 0, s>>>(d, k, X, rfac, Q, zw, gout);
   }
   return hipGetLastError();
 }
 
+template <typename TW>
+static hipError_t chol_solve_t(int batch, int64_t d, int k, int nch_in, const double* X,
+                               const double* gin, double* rfac, double* Q, TW* zw, double* gout,
+                               int32_t* flags, hipStream_t s) {
+  if (k <= 16) return chol_solve_km<TW, 16>(batch, d, k, nch_in, X, gin, rfac, Q, zw, gout, flags, s);
+  if (k <= 32) return chol_solve_km<TW, 32>(batch, d, k, nch_in, X, gin, rfac, Q, zw, gout, flags, s);
+  return chol_solve_km<TW, kMaxK>(batch, d, k, nch_in, X, gin, rfac, Q, zw, gout, flags, s);
+}
+
 int chol_solve_chunks(int64_t d, int k) {
-  const int rc = k <= 16 ? ChunkRows<16>::value : (k <= 32 ? ChunkRows<32>::value : ChunkRows<kMaxK>::value);
-  return nblk(d, rc);
+  return k <= 16 ? nblk(d, ChunkRows<16>::value) : nblk(d, kGramRows);
 }
 
 hipError_t launch_chol_solve(int batch, int64_t d, int k, int nch_in, const double* X,
-                             const double* gram_in, double* Q, void* zw, size_t zw_bytes,
-                             double* gram_out, int32_t* flags, hipStream_t s) {
+                             const double* gram_in, double* rfac, double* Q, void* zw,
+                             size_t zw_bytes, double* gram_out, int32_t* flags, hipStream_t s) {
   if (zw == nullptr || zw_bytes == 8)
-    return chol_solve_t<double>(batch, d, k, nch_in, X, gram_in, Q, (double*)zw, gram_out, flags, s);
-  return chol_solve_t<float>(batch, d, k, nch_in, X, gram_in, Q, (float*)zw, gram_out, flags, s);
+    return chol_solve_t<double>(batch, d, k, nch_in, X, gram_in, rfac, Q, (double*)zw, gram_out,
+                                flags, s);
+  return chol_solve_t<float>(batch, d, k, nch_in, X, gram_in, rfac, Q, (float*)zw, gram_out, flags,
+                             s);
 }
 
 hipError_t launch_diag_dot(int batch, int64_t d, int k, const double* Zi, const double* Zb,

@@ -109,7 +109,7 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   L.tbuf = take((size_t)n * k_max * P->acc_bytes);
   L.gram = take(mb * P->n_gram_chunks * (size_t)k_max * k_max * 8);
   L.gram2 = take(mb * P->n_gram_chunks * (size_t)k_max * k_max * 8);
-  L.rinv = take(mb * (size_t)k_max * k_max * 8);
+  L.rinv = take(mb * 2 * (size_t)k_max * k_max * 8);   // R^{-1} per matrix, then summed Grams
   L.omat = take(mb * (size_t)k_max * k_max * 8);
   L.sgn = take(mb * k_max);
   L.flags = take((mb + 2) * 4);
@@ -156,15 +156,16 @@ hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int 
   double* gram = (double*)(ws + L.gram);
   double* gram2 = (double*)(ws + L.gram2);
   double* tmp = (double*)(ws + L.tmp);
+  double* rfac = (double*)(ws + L.rinv);
   const int nch = (int)((d + kGramRows - 1) / kGramRows);
   hipError_t e;
   // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}, and the Gram partials of Q1
-  if ((e = launch_chol_solve(batch, d, k, nch, Y, gram, tmp, nullptr, 0, gram2, flags, s)) !=
+  if ((e = launch_chol_solve(batch, d, k, nch, Y, gram, rfac, tmp, nullptr, 0, gram2, flags, s)) !=
       hipSuccess)
     return e;
   // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1} (and the working copy)
-  return launch_chol_solve(batch, d, k, chol_solve_chunks(d, k), tmp, gram2, Q, zw, P.zw_bytes,
-                           nullptr, flags, s);
+  return launch_chol_solve(batch, d, k, chol_solve_chunks(d, k), tmp, gram2, rfac, Q, zw,
+                           P.zw_bytes, nullptr, flags, s);
 }
 
 hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y, double* Q,

@@ -155,10 +155,6 @@ hipError_t launch_cross_gram(int batch, int64_t d, int k, const double* X, int64
                              const double* W, int64_t w_stride, double* gram_part,
                              hipStream_t s);
 
-// R_b^{-1} (upper triangular, k x k) from the Cholesky factor of
-// G_b = sum of the gram partials; flags[b] = 1 on breakdown.
-hipError_t launch_chol_inv(int batch, int nchunks, int k, const double* gram_part,
-                           double* rinv, int32_t* flags, hipStream_t s);
 
 // Q_b = X_b S_b (d x k times k x k); S upper triangular if `upper`.
 //   S stride k*k between batches (s_stride = 0: shared).  Optionally also writes
@@ -171,9 +167,6 @@ hipError_t launch_right_mult(int batch, int64_t d, int k, const double* X, const
 hipError_t launch_sign_from_gram(int batch, int nchunks, int k, const double* gram_part,
                                  int8_t* sgn, hipStream_t s);
 
-// Scale columns of X_b by sgn (in place), rewriting the working copy.
-hipError_t launch_apply_signs(int batch, int64_t d, int k, double* X, const int8_t* sgn,
-                              void* zw, size_t zw_bytes, hipStream_t s);
 
 // Procrustes factor O_b = W1 W2^T of C_b = sum of cross-gram partials (one-sided Jacobi).
 hipError_t launch_procrustes(int batch, int nchunks, int k, const double* gram_part,
@@ -212,30 +205,17 @@ hipError_t launch_reduce_gram(const Plan& P, int k, const void* part, const int3
 hipError_t launch_aggregate_gram(int m, int64_t d, int k, const double* Yi, double scale, double* Y,
                                  double* gram, hipStream_t s);
 
-// One CholeskyQR pass from precomputed Gram partials: every workgroup sums the
-// partials of its matrix, factors G = R^T R (FP64), forms R^{-1} and writes
-// Q = X R^{-1} for its row chunk; optionally the working copy (zw) and the Gram
-// partials of Q (gram_out).  flags[b] = 1 on breakdown.
-hipError_t launch_chol_apply(int batch, int64_t d, int k, const double* X, const double* gram_in,
-                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
-                             int32_t* flags, hipStream_t s);
 
-// R^{-1} of chol(sum of Gram partials) per matrix, one wavefront each.
-hipError_t launch_chol_inv_wave(int batch, int nch, int k, const double* gram, double* rinv,
-                                int32_t* flags, hipStream_t s);
 
-// Q = X R^{-1} per row chunk (R^{-1} from rinv), optional working copy and Gram
-// partials of Q.
-hipError_t launch_apply_gram(int batch, int64_t d, int k, const double* X, const double* rinv,
-                             double* Q, void* zw, size_t zw_bytes, double* gram_out,
-                             hipStream_t s);
 
-// One CholeskyQR pass per row chunk: sum the nch_in Gram partials, factor (every
-// workgroup, one wavefront), forward-substitute the chunk's rows, optionally write
-// the working copy and the Gram partials of Q (chol_solve_chunks(d, k) of them).
+// One CholeskyQR pass: sum the nch_in Gram partials and factor them (k <= 16:
+// in every row-chunk workgroup, one launch; larger k: once per matrix into
+// rfac = batch x (k*k + k) doubles, then the row chunks), forward-substitute the
+// rows, optionally write the working copy and the Gram partials of Q
+// (chol_solve_chunks(d, k) of them).
 hipError_t launch_chol_solve(int batch, int64_t d, int k, int nch_in, const double* X,
-                             const double* gram_in, double* Q, void* zw, size_t zw_bytes,
-                             double* gram_out, int32_t* flags, hipStream_t s);
+                             const double* gram_in, double* rfac, double* Q, void* zw,
+                             size_t zw_bytes, double* gram_out, int32_t* flags, hipStream_t s);
 int chol_solve_chunks(int64_t d, int k);
 
 // Sign-fixing in two launches: column dots <Zi[:,j], Zb[:,j]> partials per row

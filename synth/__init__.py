@@ -20,9 +20,9 @@ from .workloads import (  # noqa: F401
     gaussian_start,
     fixed_schedule,
     decay_schedule,
-    make_c1,
-    make_c2,
-    make_c3,
-    make_c4,
+    make_fp64_2000x100,
+    make_fp32_262144x1024,
+    make_bf16_1048576x2048,
+    make_fp32_uneven_500000x4096,
     make_small,
 )

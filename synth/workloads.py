@@ -30,6 +30,8 @@ import torch
 # Row block used when drawing large matrices; part of the recipe (the Philox
 # stream is consumed block after block), so changing it changes the data.
 GEN_BLOCK_ROWS = 65536
+# above this many elements the low-rank generator orthonormalises U block by block
+LARGE_ELEMENTS = 1 << 30
 
 
 @dataclasses.dataclass
@@ -124,6 +126,8 @@ def lowrank_plus_noise(n: int, d: int, sigma: np.ndarray, noise: float, seed: in
     """
     if n < d:
         raise ValueError("low-rank-plus-noise needs n >= d (U is n x d orthonormal)")
+    if n * d > LARGE_ELEMENTS:
+        return _lowrank_plus_noise_blocked(n, d, sigma, noise, seed, device, dtype)
     gen = _gen(seed, device)
     V = haar(d, d, gen, device)
     U = haar(n, d, gen, device)
@@ -136,6 +140,42 @@ def lowrank_plus_noise(n: int, d: int, sigma: np.ndarray, noise: float, seed: in
             blk += noise * torch.randn(r1 - r0, d, generator=gen, dtype=torch.float64, device=device)
         out[r0:r1] = _cast(blk, dtype)
     del U
+    return out
+
+
+def _lowrank_plus_noise_blocked(n: int, d: int, sigma: np.ndarray, noise: float, seed: int,
+                                device, dtype) -> torch.Tensor:
+    """The same construction for matrices too large to orthonormalise whole.
+
+    U = X R^{-1} with X an n x d standard Gaussian and R the Cholesky factor
+    of X^T X (the Q factor of X with a positive-diagonal R, i.e. Haar), formed
+    block by block: one pass accumulates X^T X, a second pass re-draws each X
+    block from the saved generator state.  Streams: V from a generator seeded
+    with `seed`, X from `seed + 1_000_003`, the noise from `seed + 2_000_006`.
+    """
+    gen = _gen(seed, device)
+    V = haar(d, d, gen, device)
+    gx = _gen(seed + 1_000_003, device)
+    gn = _gen(seed + 2_000_006, device)
+    state = gx.get_state()
+    G = torch.zeros(d, d, dtype=torch.float64, device=device)
+    for r0 in range(0, n, GEN_BLOCK_ROWS):
+        r1 = min(n, r0 + GEN_BLOCK_ROWS)
+        X = torch.randn(r1 - r0, d, generator=gx, dtype=torch.float64, device=device)
+        G += X.T @ X
+    R = torch.linalg.cholesky(G, upper=True)
+    Rinv = torch.linalg.solve_triangular(R, torch.eye(d, dtype=torch.float64, device=device), upper=True)
+    W = (torch.as_tensor(sigma, dtype=torch.float64, device=device)[:, None] * V.T) * math.sqrt(n)
+    M = Rinv @ W
+    gx.set_state(state)
+    out = torch.empty(n, d, dtype=dtype, device=device)
+    for r0 in range(0, n, GEN_BLOCK_ROWS):
+        r1 = min(n, r0 + GEN_BLOCK_ROWS)
+        X = torch.randn(r1 - r0, d, generator=gx, dtype=torch.float64, device=device)
+        blk = X @ M
+        if noise != 0.0:
+            blk += noise * torch.randn(r1 - r0, d, generator=gn, dtype=torch.float64, device=device)
+        out[r0:r1] = _cast(blk, dtype)
     return out
 
 
@@ -219,7 +259,7 @@ def decay_schedule(stages: Sequence[int], rounds_per_stage: int) -> List[int]:
 # named workloads
 # --------------------------------------------------------------------------
 
-def make_c1(device="cpu", seed: int = 0, mode: str = "sign", p: int = 4, rounds: int = 30) -> Workload:
+def make_fp64_2000x100(device="cpu", seed: int = 0, mode: str = "sign", p: int = 4, rounds: int = 30) -> Workload:
     """Plain FP64: A 2000 x 100 low-rank-plus-noise, k=5, m=4 x 500 rows."""
     n, d, k, m = 2000, 100, 5, 4
     sig = spectrum_c1(d, k)
@@ -228,7 +268,7 @@ def make_c1(device="cpu", seed: int = 0, mode: str = "sign", p: int = 4, rounds:
                     fixed_schedule(p, rounds), mode, gaussian_start(d, k, seed), sig, seed)
 
 
-def make_c2(device="cuda", seed: int = 1, mode: str = "sign", p: int = 4, rounds: int = 50,
+def make_fp32_262144x1024(device="cuda", seed: int = 1, mode: str = "sign", p: int = 4, rounds: int = 50,
             n: int = 262144, d: int = 1024, k: int = 16, m: int = 32) -> Workload:
     """FP32 fused path: A 262144 x 1024 FP32, gap sigma_16/sigma_17 = 1.2, k=16, m=32."""
     sig = spectrum_gap(d, k, 1.2, 0.97)
@@ -237,7 +277,7 @@ def make_c2(device="cuda", seed: int = 1, mode: str = "sign", p: int = 4, rounds
                     fixed_schedule(p, rounds), mode, gaussian_start(d, k, seed), sig, seed)
 
 
-def make_c3(device="cuda", seed: int = 2, mode: str = "opt", dtype=torch.bfloat16,
+def make_bf16_1048576x2048(device="cuda", seed: int = 2, mode: str = "opt", dtype=torch.bfloat16,
             n: int = 1048576, d: int = 2048, k: int = 32, m: int = 64) -> Workload:
     """Precision form: Gaussian rows with covariance spectrum j^-1.5, stored BF16."""
     lam = power_law_cov(d, 1.5)
@@ -248,7 +288,7 @@ def make_c3(device="cuda", seed: int = 2, mode: str = "opt", dtype=torch.bfloat1
                     np.sqrt(lam), seed)
 
 
-def make_c4(device="cuda", seed: int = 3, mode: str = "opt", rounds: int = 30,
+def make_fp32_uneven_500000x4096(device="cuda", seed: int = 3, mode: str = "opt", rounds: int = 30,
             n: int = 500000, d: int = 4096, k: int = 64, m: int = 100) -> Workload:
     """Uneven partitions: A 500000 x 4096 FP32, m=100 lognormal row counts, k=64."""
     sig = spectrum_gap(d, k, 1.2, 0.97)

@@ -61,17 +61,17 @@ def test_fused_other_k_falls_back(lp):
 
 
 @pytest.fixture(scope="module")
-def c2(lp):
+def fp32_dense(lp):
     print("generating the 262144 x 1024 FP32 workload", flush=True)
-    w = synth.make_c2(device="cuda:0", rounds=3)
+    w = synth.make_fp32_262144x1024(device="cuda:0", rounds=3)
     return w
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_fused_full_size_sampled(lp, c2, variant):
+def test_fused_full_size_sampled(lp, fp32_dense, variant):
     """Bench shape, the launch configuration the benchmark times: sampled partitions."""
     print(f"full-size local multiply variant={variant}", flush=True)
-    w = c2
+    w = fp32_dense
     P = lp.lp_create(w.A, w.offsets, 16)
     lp.lp_set_tuning(P, variant, 0)
     Z = oracle.orth(np.random.default_rng(5).standard_normal((w.d, 16)))
@@ -88,11 +88,11 @@ def test_fused_full_size_sampled(lp, c2, variant):
         assert np.all(np.abs(Y[i] - ref) <= (w.d + A[i].shape[0]) * u * bound)
 
 
-def test_full_size_run_parity(lp, c2):
+def test_full_size_run_parity(lp, fp32_dense):
     """Three rounds of p = 4 sign-fixing at the bench shape against the oracle on
     the same FP32 values: subspace within 1e-5, sign decisions bit-exact."""
     print("full-size run vs oracle", flush=True)
-    w = c2
+    w = fp32_dense
     P = lp.lp_create(w.A, w.offsets, 16)
     r = lp.lp_run(P, 16, w.p_sched, "sign", w.Y0, record_signs=True)
     A = w.A.to("cpu").to(torch.float64).numpy()

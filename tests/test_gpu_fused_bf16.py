@@ -85,17 +85,17 @@ def test_bf16_other_k_falls_back(lp):
 
 
 @pytest.fixture(scope="module")
-def c3(lp):
+def bf16_wide(lp):
     print("generating the 1048576 x 2048 BF16 workload", flush=True)
-    return synth.make_c3(device="cuda:0")
+    return synth.make_bf16_1048576x2048(device="cuda:0")
 
 
 @pytest.mark.parametrize("variant", [2, 3])
-def test_bf16_fused_full_size_sampled(lp, c3, variant):
+def test_bf16_fused_full_size_sampled(lp, bf16_wide, variant):
     """Precision-form shape (64 partitions of 16384 x 2048, k = 32), the launch
     configuration the benchmark times: three sampled partitions."""
     print(f"bf16 full-size local multiply variant={variant}", flush=True)
-    w = c3
+    w = bf16_wide
     P = lp.lp_create(w.A, w.offsets, w.k)
     lp.lp_set_tuning(P, variant, 0)
     Z = oracle.orth(np.random.default_rng(7).standard_normal((w.d, w.k)))

@@ -57,17 +57,17 @@ def test_gemm_small(lp, d, k, dtype):
 
 
 @pytest.fixture(scope="module")
-def c4(lp):
+def fp32_uneven(lp):
     print("generating the 500000 x 4096 uneven-partition workload", flush=True)
-    return synth.make_c4(device="cuda:0")
+    return synth.make_fp32_uneven_500000x4096(device="cuda:0")
 
 
-def test_gemm_full_size_sampled(lp, c4):
+def test_gemm_full_size_sampled(lp, fp32_uneven):
     """500000 x 4096 FP32, k = 64, 100 lognormal partitions (the launch
     configuration the uneven-partition benchmark times): the smallest, the
     largest and a middle partition."""
     print("two-pass full size", flush=True)
-    w = c4
+    w = fp32_uneven
     P = lp.lp_create(w.A, w.offsets, w.k)
     Z = oracle.orth(np.random.default_rng(11).standard_normal((w.d, w.k)))
     Y = host(lp.lp_local_multiply(P, w.k, torch.as_tensor(Z)))

@@ -33,19 +33,19 @@ def lib(gpu_lib):
 
 
 @pytest.fixture(scope="module")
-def c1():
-    w = synth.make_c1()
+def fp64_small():
+    w = synth.make_fp64_2000x100()
     A = w.A.numpy()
     U, lam = oracle.top_k(A, w.k)
     return w, A, U, lam
 
 
-# --------------------------------------------------------------------- C1 (FP64)
+# --------------------------------------------------------------------- FP64 2000 x 100
 
 @pytest.mark.parametrize("mode", ["sign", "opt", "vanilla"])
-def test_c1_full_run(lib, c1, mode):
-    w, A, U, lam = c1
-    _flush(f"c1 mode={mode}")
+def test_fp64_small_full_run(lib, fp64_small, mode):
+    w, A, U, lam = fp64_small
+    _flush(f"fp64_small mode={mode}")
     P = _problem(lib, to_device(w), w.offsets, w.k)
     r = lib.lp_run(P, w.k, w.p_sched, mode, w.Y0, U_ref=torch.as_tensor(U), record_signs=True)
     ro = oracle.localpower(A, w.offsets, w.k, w.p_sched, mode, w.Y0, U_ref=U)
@@ -61,9 +61,9 @@ def test_c1_full_run(lib, c1, mode):
     assert st["rounds"] == 30 and st["local_iters"] == 120 and st["breakdowns"] == 0
 
 
-def test_c1_p1_is_dpi(lib, c1):
-    w, A, U, lam = c1
-    _flush("c1 p=1")
+def test_fp64_small_p1_is_dpi(lib, fp64_small):
+    w, A, U, lam = fp64_small
+    _flush("fp64_small p=1")
     P = _problem(lib, to_device(w), w.offsets, w.k)
     r = lib.lp_run(P, w.k, [1] * 30, "sign", w.Y0)
     Zd, _ = oracle.dpi(A, w.Y0, 30)
@@ -71,9 +71,9 @@ def test_c1_p1_is_dpi(lib, c1):
     assert sin_theta_np(host(r["Z"]), U) < 1e-12
 
 
-def test_c1_decay_and_ritz(lib, c1):
-    w, A, U, lam = c1
-    _flush("c1 decay+ritz")
+def test_fp64_small_decay_and_ritz(lib, fp64_small):
+    w, A, U, lam = fp64_small
+    _flush("fp64_small decay+ritz")
     sched = synth.decay_schedule((8, 4, 2, 1), 10)
     P = _problem(lib, to_device(w), w.offsets, w.k)
     r = lib.lp_run(P, w.k, sched, "opt", w.Y0, ritz=True)
@@ -215,8 +215,8 @@ def test_bf16_run_parity(lib):
 
 # --------------------------------------------------------------------- runtime properties
 
-def test_graph_plain_and_repeat_bitwise(lib, c1):
-    w, A, U, lam = c1
+def test_graph_plain_and_repeat_bitwise(lib, fp64_small):
+    w, A, U, lam = fp64_small
     _flush("graph vs plain")
     P = _problem(lib, to_device(w), w.offsets, w.k)
     r1 = lib.lp_run(P, w.k, w.p_sched, "opt", w.Y0, use_graph=True)
@@ -225,10 +225,10 @@ def test_graph_plain_and_repeat_bitwise(lib, c1):
     assert torch.equal(r1["Z"], r2["Z"]) and torch.equal(r1["Z"], r3["Z"])
 
 
-def test_resume_bitwise(lib, c1):
+def test_resume_bitwise(lib, fp64_small):
     """State at a round boundary is Z alone: resuming from the saved Z gives the
     uninterrupted result bit for bit."""
-    w, A, U, lam = c1
+    w, A, U, lam = fp64_small
     _flush("resume")
     P = _problem(lib, to_device(w), w.offsets, w.k)
     full = lib.lp_run(P, w.k, [4] * 12, "sign", w.Y0)
@@ -237,8 +237,8 @@ def test_resume_bitwise(lib, c1):
     assert torch.equal(full["Z"], rest["Z"])
 
 
-def test_invalid_arguments(lib, c1):
-    w, A, U, lam = c1
+def test_invalid_arguments(lib, fp64_small):
+    w, A, U, lam = fp64_small
     _flush("invalid args")
     P = _problem(lib, to_device(w), w.offsets, w.k)
     with pytest.raises(lib.LPError):
@@ -270,10 +270,10 @@ def test_create_right_after_queued_work(lib):
     assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
 
 
-def test_timed_graph_rounds(lib, c1):
+def test_timed_graph_rounds(lib, fp64_small):
     """Timing the local multiply inside replayed graphs changes nothing in the
     result, times every launch, and keeps the rounds on graphs."""
-    w, A, U, lam = c1
+    w, A, U, lam = fp64_small
     _flush("timed graphs")
     sched = synth.decay_schedule((8, 4, 2, 1), 5)
     P = _problem(lib, to_device(w), w.offsets, w.k)

@@ -19,7 +19,7 @@ from oracle.localpower import sign_ambiguous
 
 
 def _c1():
-    w = synth.make_c1()
+    w = synth.make_fp64_2000x100()
     A = w.A.numpy()
     U, lam = oracle.top_k(A, w.k)
     return w, A, U, lam
