@@ -216,6 +216,84 @@ lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters,
 lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
                        void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: many LocalPower jobs on one GPU.  (Runtime around the method, not
+ * part of the paper.)  A server admits submitted jobs in order while their
+ * device-memory footprint fits its budget and it has a free slot, runs one
+ * communication round at a time for every admitted job, each job on its own
+ * stream so that rounds of different jobs overlap on the GPU, admits waiting
+ * jobs as soon as others finish (continuous batching), and ends every job by
+ * its own stop rule.  A worker thread of the server does all GPU work.
+ *
+ * Per-job schedule and stop rule.  The job starts from Z_0 = orth(Y0) with
+ * p = p0 local steps per round.  After round r the change
+ * c_r = sin theta_k(Z_r, Z_{r-1}) (Definition 1) is measured; with the
+ * contraction ratio q = c_r / c_{r-1}:
+ *   - the iterates have settled when c_r q / (1 - q) <= target with q < 1 (the
+ *     tail of a geometric series of changes with ratio q, an estimate of the
+ *     remaining distance to the limit of the current p), or when c_r == 0;
+ *   - settled at p = 1, the job ends with LP_OK;
+ *   - settled at p > 1, or a round with q > 0.5 (a stall), halves p: the limit
+ *     of a fixed p > 1 sits at an error floor set by the heterogeneity of the
+ *     partitions, and p = 1 has none (the decaying p of Sections 3 and 5);
+ *   - after max_rounds rounds the job ends with LP_ENOTCONV.
+ * Z_out then holds the last iterate.  Results of a job do not depend on what
+ * else the server runs (bitwise): every job has its own workspace and stream.
+ * --------------------------------------------------------------------------- */
+typedef struct lp_server lp_server; /* opaque */
+
+typedef struct {
+  int32_t struct_size;     /* sizeof(lp_job) */
+  const void* A;           /* device n x d row-major (leading dimension lda, 16-byte
+                              aligned rows), BORROWED until the job's result is polled */
+  lp_dtype dtype;
+  int64_t n, d, lda;
+  const int64_t* offsets;  /* host, m + 1 entries as for lp_create; COPIED at submit */
+  int32_t m;
+  int32_t k;               /* 1 <= k <= min(d, 64), every partition has >= k rows */
+  int32_t p0;              /* local steps of the first round, >= 1 */
+  lp_agg mode;
+  double target;           /* > 0 */
+  int32_t max_rounds;      /* >= 1 */
+  const double* Y0;        /* host d x k FP64 start, COPIED at submit; orthonormalised */
+  double* Z_out;           /* device d x k FP64, caller-owned, written when the job ends */
+} lp_job;
+
+typedef struct {
+  uint64_t id;
+  lp_status status;        /* LP_OK, LP_ENOTCONV, LP_EBREAKDOWN or LP_EDEVICE */
+  int32_t rounds;          /* communication rounds run */
+  int32_t local_iters;     /* local steps run (sum of p over the rounds) */
+  int32_t p_final;         /* p of the last round */
+  double change;           /* last c_r */
+  double estimate;         /* last c_r q / (1 - q) (c_r when q >= 1 or r = 1) */
+  double ms_queued;        /* submission -> admission, host clock */
+  double ms_total;         /* submission -> result published */
+} lp_job_result;
+
+/* Device bytes the server allocates for `job` (its lp_workspace_size plus the
+ * start, previous-iterate and change buffers); A and Z_out are the caller's. */
+lp_status lp_server_footprint(const lp_job* job, size_t* bytes);
+
+/* Create a server on the current HIP device with a device-memory budget and at
+ * most max_active (1..64) jobs admitted at once; starts its worker thread. */
+lp_status lp_server_create(lp_server** out, size_t hbm_budget_bytes, int32_t max_active);
+
+/* Queue a job (non-blocking).  LP_EINVAL for an invalid job, LP_ENOMEM when its
+ * footprint alone exceeds the budget (it could never be admitted). */
+lp_status lp_server_submit(lp_server* S, const lp_job* job, uint64_t* job_id);
+
+/* Move up to `max` finished results into out[0 .. *n_done) (non-blocking). */
+lp_status lp_server_poll(lp_server* S, lp_job_result* out, int32_t max, int32_t* n_done);
+
+/* Block until at least min_done results are waiting to be polled, or
+ * timeout_s seconds pass (then LP_EBUSY). */
+lp_status lp_server_wait(lp_server* S, int32_t min_done, double timeout_s);
+
+/* Finish every admitted job, drop the queued ones, stop the worker and free
+ * the server.  Unpolled results are discarded. */
+lp_status lp_server_destroy(lp_server* S);
+
 #ifdef __cplusplus
 }
 #endif

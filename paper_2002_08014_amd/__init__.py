@@ -7,6 +7,7 @@ PyTorch supplies device memory and streams only.
 from ._lib import (  # noqa: F401
     LPError,
     Problem,
+    Server,
     load,
     lp_workspace_size,
     lp_create,

@@ -24,7 +24,9 @@ MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_local_multiply", "lp_orth", "lp_align",
-           "lp_sin_theta", "lp_bandwidth_probe", "lp_copy_probe")
+           "lp_sin_theta", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
+           "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
+           "lp_server_destroy")
 
 
 class LPError(RuntimeError):
@@ -61,6 +63,36 @@ class RunStats(ctypes.Structure):
                 ("ms_local", ctypes.c_double),
                 ("local_launches", ctypes.c_int32),
                 ("graph_rounds", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32),
+                ("A", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32),
+                ("n", ctypes.c_int64),
+                ("d", ctypes.c_int64),
+                ("lda", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p),
+                ("m", ctypes.c_int32),
+                ("k", ctypes.c_int32),
+                ("p0", ctypes.c_int32),
+                ("mode", ctypes.c_int32),
+                ("target", ctypes.c_double),
+                ("max_rounds", ctypes.c_int32),
+                ("Y0", ctypes.c_void_p),
+                ("Z_out", ctypes.c_void_p)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64),
+                ("status", ctypes.c_int32),
+                ("rounds", ctypes.c_int32),
+                ("local_iters", ctypes.c_int32),
+                ("p_final", ctypes.c_int32),
+                ("change", ctypes.c_double),
+                ("estimate", ctypes.c_double),
+                ("ms_queued", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -106,6 +138,18 @@ def load() -> ctypes.CDLL:
     L.lp_copy_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_sin_theta.restype = i32
     L.lp_sin_theta.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.lp_server_footprint.restype = i32
+    L.lp_server_footprint.argtypes = [ctypes.POINTER(Job), ctypes.POINTER(sz)]
+    L.lp_server_create.restype = i32
+    L.lp_server_create.argtypes = [ctypes.POINTER(vp), sz, i32]
+    L.lp_server_submit.restype = i32
+    L.lp_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+    L.lp_server_poll.restype = i32
+    L.lp_server_poll.argtypes = [vp, ctypes.POINTER(JobResult), i32, ctypes.POINTER(i32)]
+    L.lp_server_wait.restype = i32
+    L.lp_server_wait.argtypes = [vp, i32, ctypes.c_double]
+    L.lp_server_destroy.restype = i32
+    L.lp_server_destroy.argtypes = [vp]
     _LIB = L
     return L
 
@@ -321,3 +365,86 @@ def lp_copy_probe(dst: torch.Tensor, src: torch.Tensor, iters: int = 5,
     _check(L.lp_copy_probe(_ptr(dst), _ptr(src), nbytes, iters, ctypes.byref(out),
                            _stream_handle(stream)), "lp_copy_probe")
     return float(out.value)
+
+
+# ----------------------------------------------------------------------------- serving
+
+class Server:
+    """A LocalPower job server on the current device (lp_server_*).
+
+    submit() keeps A, the start matrix and the output alive until the job's
+    result has been polled; poll() returns finished jobs with their Z."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 8):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.lp_server_create(ctypes.byref(h), int(hbm_budget_bytes), int(max_active)),
+               "lp_server_create")
+        self.handle = h
+        self._jobs = {}
+
+    @staticmethod
+    def _job(A: torch.Tensor, offsets: Sequence[int], k: int, p0: int, mode: str, target: float,
+             max_rounds: int, Y0, Z_out: Optional[torch.Tensor]):
+        if A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("A must be a 2-D tensor with contiguous rows")
+        if not A.is_cuda:
+            raise ValueError("A must be a device tensor")
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        y0 = np.ascontiguousarray(np.asarray(Y0, dtype=np.float64))
+        n, d = A.shape
+        if y0.shape != (d, k):
+            raise ValueError("Y0 must be d x k")
+        Z = Z_out if Z_out is not None else torch.empty(d, k, dtype=torch.float64, device=A.device)
+        job = Job(ctypes.sizeof(Job), A.data_ptr(), DTYPES[A.dtype], n, d, A.stride(0),
+                  offs.ctypes.data, len(offs) - 1, k, p0, MODES[mode], float(target), int(max_rounds),
+                  y0.ctypes.data, Z.data_ptr())
+        return job, (A, offs, y0, Z)
+
+    @staticmethod
+    def footprint(A: torch.Tensor, offsets: Sequence[int], k: int) -> int:
+        job, keep = Server._job(A, offsets, k, 1, "sign", 1e-4, 1, np.zeros((A.shape[1], k)), None)
+        out = ctypes.c_size_t()
+        _check(load().lp_server_footprint(ctypes.byref(job), ctypes.byref(out)), "lp_server_footprint")
+        return out.value
+
+    def submit(self, A: torch.Tensor, offsets: Sequence[int], k: int, Y0, p0: int = 4,
+               mode: str = "sign", target: float = 1e-4, max_rounds: int = 200,
+               Z_out: Optional[torch.Tensor] = None) -> int:
+        job, keep = self._job(A, offsets, k, p0, mode, target, max_rounds, Y0, Z_out)
+        jid = ctypes.c_uint64()
+        _check(load().lp_server_submit(self.handle, ctypes.byref(job), ctypes.byref(jid)),
+               "lp_server_submit")
+        self._jobs[jid.value] = keep
+        return jid.value
+
+    def poll(self, max_results: int = 256) -> list:
+        buf = (JobResult * max_results)()
+        n = ctypes.c_int32()
+        _check(load().lp_server_poll(self.handle, buf, max_results, ctypes.byref(n)), "lp_server_poll")
+        out = []
+        for r in buf[:n.value]:
+            keep = self._jobs.pop(r.id)
+            out.append({"id": r.id, "status": r.status, "rounds": r.rounds, "local_iters": r.local_iters,
+                        "p_final": r.p_final, "change": r.change, "estimate": r.estimate,
+                        "ms_queued": r.ms_queued, "ms_total": r.ms_total, "Z": keep[3]})
+        return out
+
+    def wait(self, min_done: int, timeout_s: float = 60.0) -> bool:
+        st = load().lp_server_wait(self.handle, int(min_done), float(timeout_s))
+        if st == LP_EBUSY:
+            return False
+        _check(st, "lp_server_wait")
+        return True
+
+    def close(self) -> None:
+        if self.handle is not None:
+            _check(load().lp_server_destroy(self.handle), "lp_server_destroy")
+            self.handle = None
+            self._jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

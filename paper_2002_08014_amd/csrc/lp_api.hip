@@ -431,6 +431,53 @@ lp_status check_k(lp_problem* P, int32_t k) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Step-wise driving (the serving layer runs many problems one round at a time;
+// everything is enqueued on the problem's own stream, nothing synchronises).
+// ---------------------------------------------------------------------------
+namespace lp {
+
+lp_status drive_begin(lp_problem* P, int k, const double* Y0, bool orthonormal) {
+  lp_status st = check_k(P, k);
+  if (st != LP_OK) return st;
+  Ptrs q = ptrs(P);
+  hipStream_t s = P->stream;
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(launch_fill_i32(q.flags, P->m + 2, 0, s));
+  LP_HIP(launch_fill_i32(q.ctr, 1, 0, s));
+  if (orthonormal) {
+    LP_HIP(hipMemcpyAsync(q.Z, Y0, (size_t)P->d * k * 8, hipMemcpyDeviceToDevice, s));
+    LP_HIP(launch_to_working(P->plan, 1, P->d, k, q.Z, q.Zw_shared, s));
+  } else {
+    LP_HIP(cholqr2(P->plan, P->ws, 1, P->d, k, Y0, q.Z, q.Zw_shared, q.flags + P->m, s));
+  }
+  return LP_OK;
+}
+
+lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode) {
+  if (p < 1) return fail(LP_EINVAL, "p must be >= 1");
+  return run_round(P, k, p, mode, false, true, -1);
+}
+
+const double* drive_z(lp_problem* P) { return ptrs(P).Z; }
+
+lp_status report(lp_status s, const std::string& msg) { return fail(s, msg); }
+
+hipStream_t drive_stream(lp_problem* P) { return P->stream; }
+
+lp_status drive_breakdowns(lp_problem* P, int* breakdowns) {
+  Ptrs q = ptrs(P);
+  std::vector<int32_t> flags(P->m + 2, 0);
+  LP_HIP(hipMemcpyAsync(flags.data(), q.flags, (P->m + 2) * 4, hipMemcpyDeviceToHost, P->stream));
+  LP_HIP(hipStreamSynchronize(P->stream));
+  int b = 0;
+  for (int i = 0; i < P->m + 1; ++i) b += flags[i];
+  *breakdowns = b;
+  return LP_OK;
+}
+
+}  // namespace lp
+
 extern "C" {
 
 const char* lp_strerror(lp_status s) {

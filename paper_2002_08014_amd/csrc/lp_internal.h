@@ -104,6 +104,19 @@ struct lp_problem {
 
 namespace lp {
 
+// Step-wise driving of a problem (the serving layer): begin sets Z = orth(Y0)
+// (or copies Y0 when it is already orthonormal) and clears the flags; round
+// enqueues one communication round with p local steps (graph-replayed); the
+// current iterate is drive_z; drive_breakdowns synchronises and counts the
+// breakdown flags.  Everything runs on drive_stream(P).
+lp_status drive_begin(lp_problem* P, int k, const double* Y0, bool orthonormal);
+lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode);
+const double* drive_z(lp_problem* P);
+hipStream_t drive_stream(lp_problem* P);
+lp_status drive_breakdowns(lp_problem* P, int* breakdowns);
+// Record msg as the thread's last error (lp_last_error) and return s.
+lp_status report(lp_status s, const std::string& msg);
+
 // ---------------------------------------------------------------------------
 // kernel launchers (all enqueue on `s`, return the launch status)
 // ---------------------------------------------------------------------------

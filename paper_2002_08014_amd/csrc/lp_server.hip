@@ -1,0 +1,398 @@
+// Serving layer: many LocalPower jobs on one GPU (host code only).
+//
+// One worker thread owns all GPU work.  Jobs wait in a FIFO until their
+// device footprint fits the budget and a slot is free (admission); an
+// admitted job gets a slot (a stream for its allocations and a pinned change
+// cell), one stream-ordered allocation for its workspace and small buffers,
+// and an lp_problem with its own stream.  The worker keeps one round in
+// flight per job: a round, the change sin theta(Z_r, Z_{r-1}) into pinned
+// memory and an event; it polls the events, applies the per-job stop rule,
+// halves p on a stall, and enqueues the next round.  Rounds of different jobs
+// therefore overlap on the GPU, and a finished job's slot is refilled at once
+// from the queue (continuous batching).
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+
+#include "lp_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Job {
+  uint64_t id = 0;
+  lp_job spec;
+  std::vector<int64_t> offsets;
+  std::vector<double> y0;
+  size_t ws_bytes = 0, footprint = 0;
+  Clock::time_point t_submit, t_admit;
+  // set at admission
+  int slot = -1;
+  char* mem = nullptr;
+  lp_problem* P = nullptr;
+  double* y0_dev = nullptr;
+  double* zprev = nullptr;
+  double* change_dev = nullptr;
+  // schedule state
+  int p = 1, rounds = 0, iters = 0;
+  double prev_change = -1.0, change = 0.0, estimate = 0.0;
+  bool in_flight = false;
+};
+
+}  // namespace
+
+struct lp_server {
+  int device = 0;
+  size_t budget = 0, used = 0;
+  int max_active = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job*> queue;
+  std::deque<lp_job_result> done;
+  uint64_t next_id = 1;
+  bool stopping = false;
+  // owned by the worker thread
+  std::vector<Job*> active;
+  std::vector<hipStream_t> slot_stream;
+  std::vector<hipEvent_t> slot_event;
+  std::vector<int> free_slots;
+  double* pinned = nullptr;   // one change cell per slot
+  std::thread worker;
+};
+
+namespace {
+
+lp_status validate(const lp_job* j) {
+  if (j == nullptr || j->struct_size < (int32_t)sizeof(lp_job)) return lp::report(LP_EINVAL, "job is NULL or struct_size too small");
+  if (j->A == nullptr || j->offsets == nullptr || j->Y0 == nullptr || j->Z_out == nullptr)
+    return lp::report(LP_EINVAL, "A, offsets, Y0 and Z_out are required");
+  if (j->n < 1 || j->d < 1 || j->lda < j->d || j->m < 1) return lp::report(LP_EINVAL, "bad n, d, lda or m");
+  if (j->k < 1 || j->k > 64 || j->k > j->d) return lp::report(LP_EINVAL, "need 1 <= k <= min(d, 64)");
+  if (j->p0 < 1 || j->max_rounds < 1 || !(j->target > 0.0)) return lp::report(LP_EINVAL, "need p0 >= 1, max_rounds >= 1, target > 0");
+  if (j->mode != LP_AGG_VANILLA && j->mode != LP_AGG_SIGN && j->mode != LP_AGG_OPT) return lp::report(LP_EINVAL, "unknown mode");
+  if (j->offsets[0] != 0 || j->offsets[j->m] != j->n) return lp::report(LP_EINVAL, "offsets must run from 0 to n");
+  for (int i = 0; i < j->m; ++i)
+    if (j->offsets[i + 1] - j->offsets[i] < j->k) return lp::report(LP_EINVAL, "every partition needs at least k rows");
+  return LP_OK;
+}
+
+// bytes of the per-job buffers after the workspace: Y0, previous Z, change cell
+size_t extra_bytes(const lp_job* j) { return 2 * round_up((size_t)j->d * j->k * 8, 256) + 256; }
+
+void publish(lp_server* S, Job* j, lp_status st) {
+  lp_job_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.id = j->id;
+  r.status = st;
+  r.rounds = j->rounds;
+  r.local_iters = j->iters;
+  r.p_final = j->p;
+  r.change = j->change;
+  r.estimate = j->estimate;
+  const Clock::time_point now = Clock::now();
+  r.ms_queued = ms_between(j->t_submit, j->t_admit);
+  r.ms_total = ms_between(j->t_submit, now);
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->used -= j->footprint;
+    S->done.push_back(r);
+  }
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+}
+
+// release the job's GPU resources (its stream has been synchronised)
+void release(lp_server* S, Job* j) {
+  if (j->P != nullptr) (void)lp_destroy(j->P);
+  j->P = nullptr;
+  if (j->mem != nullptr) (void)hipFreeAsync(j->mem, S->slot_stream[j->slot]);
+  j->mem = nullptr;
+  S->free_slots.push_back(j->slot);
+  j->slot = -1;
+}
+
+// end the job: copy Z_out, check breakdown flags, free, publish
+void finish(lp_server* S, Job* j, lp_status st) {
+  if (j->P != nullptr) {
+    hipStream_t s = lp::drive_stream(j->P);
+    if (hipMemcpyAsync(j->spec.Z_out, lp::drive_z(j->P), (size_t)j->spec.d * j->spec.k * 8,
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+      st = LP_EDEVICE;
+    int breakdowns = 0;
+    if (lp::drive_breakdowns(j->P, &breakdowns) != LP_OK) st = LP_EDEVICE;
+    else if (breakdowns > 0 && st == LP_OK) st = LP_EBREAKDOWN;
+  }
+  release(S, j);
+  publish(S, j, st);
+  delete j;
+}
+
+// one round, the change and its copy to the job's pinned cell, then the event
+lp_status launch(lp_server* S, Job* j) {
+  lp_problem* P = j->P;
+  hipStream_t s = lp::drive_stream(P);
+  const int64_t dk = j->spec.d * j->spec.k;
+  lp_status st = lp::drive_round(P, j->spec.k, j->p, j->spec.mode);
+  if (st != LP_OK) return st;
+  if (lp::launch_sin_theta(j->spec.d, j->spec.k, lp::drive_z(P), j->zprev, j->change_dev, nullptr,
+                           nullptr, s) != hipSuccess ||
+      hipMemcpyAsync(j->zprev, lp::drive_z(P), dk * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(S->pinned + j->slot, j->change_dev, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipEventRecord(S->slot_event[j->slot], s) != hipSuccess)
+    return lp::report(LP_EDEVICE, "serving: enqueue failed");
+  j->in_flight = true;
+  return LP_OK;
+}
+
+// admission work for one job: memory, problem, Z_0 = orth(Y0), first round
+lp_status start(lp_server* S, Job* j) {
+  if (S->free_slots.empty()) return lp::report(LP_EDEVICE, "serving: no free slot");
+  j->slot = S->free_slots.back();
+  S->free_slots.pop_back();
+  hipStream_t ss = S->slot_stream[j->slot];
+  if (hipMallocAsync((void**)&j->mem, j->footprint, ss) != hipSuccess) {
+    j->mem = nullptr;
+    return lp::report(LP_EDEVICE, "serving: allocation failed");
+  }
+  const lp_job& sp = j->spec;
+  lp_status st = lp_create(&j->P, sp.A, sp.dtype, sp.n, sp.d, sp.lda, j->offsets.data(), sp.m,
+                           sp.k, j->mem, j->ws_bytes, ss);
+  if (st != LP_OK) {
+    j->P = nullptr;
+    return st;
+  }
+  const size_t dk8 = round_up((size_t)sp.d * sp.k * 8, 256);
+  j->y0_dev = (double*)(j->mem + j->ws_bytes);
+  j->zprev = (double*)(j->mem + j->ws_bytes + dk8);
+  j->change_dev = (double*)(j->mem + j->ws_bytes + 2 * dk8);
+  hipStream_t s = lp::drive_stream(j->P);
+  if (hipMemcpyAsync(j->y0_dev, j->y0.data(), (size_t)sp.d * sp.k * 8, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return lp::report(LP_EDEVICE, "serving: start copy failed");
+  if ((st = lp::drive_begin(j->P, sp.k, j->y0_dev, false)) != LP_OK) return st;
+  if (hipMemcpyAsync(j->zprev, lp::drive_z(j->P), (size_t)sp.d * sp.k * 8, hipMemcpyDeviceToDevice,
+                     s) != hipSuccess)
+    return lp::report(LP_EDEVICE, "serving: start copy failed");
+  j->p = sp.p0;
+  return launch(S, j);
+}
+
+// a round of job j has completed: stop rule, stall rule, next round.  Returns
+// false when the job has ended (it is then published and deleted).
+bool advance(lp_server* S, Job* j) {
+  j->in_flight = false;
+  j->change = S->pinned[j->slot];
+  j->rounds++;
+  j->iters += j->p;
+  double q = 1.0;
+  if (j->prev_change > 0.0) q = j->change / j->prev_change;
+  j->estimate = (j->prev_change > 0.0 && q < 1.0) ? j->change * q / (1.0 - q) : j->change;
+  const bool settled =
+      j->change == 0.0 || (j->prev_change > 0.0 && q < 1.0 && j->estimate <= j->spec.target);
+  j->prev_change = j->change;
+  // settled at p = 1: done.  Settled at p > 1 only means the iterates reached
+  // the fixed point of this p, which sits at an error floor: halve p.
+  if (settled && j->p == 1) {
+    finish(S, j, LP_OK);
+    return false;
+  }
+  if (j->rounds >= j->spec.max_rounds) {
+    finish(S, j, LP_ENOTCONV);
+    return false;
+  }
+  if (j->p > 1 && (settled || (j->rounds >= 2 && q > 0.5))) j->p = std::max(1, j->p / 2);
+  lp_status st = launch(S, j);
+  if (st != LP_OK) {
+    finish(S, j, st);
+    return false;
+  }
+  return true;
+}
+
+void worker_main(lp_server* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    std::vector<Job*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->stopping) {
+        for (Job* j : S->queue) {
+          S->used -= j->footprint;
+          delete j;
+        }
+        S->queue.clear();
+        if (S->active.empty()) break;
+      }
+      // a job is admitted only with a slot reserved for it (slots are taken in start())
+      while (!S->queue.empty() && admitted.size() < S->free_slots.size() &&
+             S->used + S->queue.front()->footprint <= S->budget) {
+        Job* j = S->queue.front();
+        S->queue.pop_front();
+        S->used += j->footprint;
+        admitted.push_back(j);
+      }
+      if (admitted.empty() && S->active.empty()) {
+        S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        continue;
+      }
+    }
+    for (Job* j : admitted) {
+      j->t_admit = Clock::now();
+      lp_status st = start(S, j);
+      if (st != LP_OK) {
+        if (j->P != nullptr) (void)hipStreamSynchronize(lp::drive_stream(j->P));
+        if (j->slot >= 0) release(S, j);
+        publish(S, j, st);
+        delete j;
+        continue;
+      }
+      S->active.push_back(j);
+    }
+    bool progressed = !admitted.empty();
+    for (size_t a = 0; a < S->active.size();) {
+      Job* j = S->active[a];
+      const hipError_t q = hipEventQuery(S->slot_event[j->slot]);
+      if (q == hipErrorNotReady) {
+        ++a;
+        continue;
+      }
+      progressed = true;
+      bool keep = false;
+      if (q != hipSuccess)
+        finish(S, j, lp::report(LP_EDEVICE, std::string("serving: ") + hipGetErrorString(q)));
+      else
+        keep = advance(S, j);
+      if (keep)
+        ++a;
+      else
+        S->active.erase(S->active.begin() + a);
+    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lp_status lp_server_footprint(const lp_job* job, size_t* bytes) {
+  if (bytes == nullptr) return lp::report(LP_EINVAL, "bytes is NULL");
+  lp_status st = validate(job);
+  if (st != LP_OK) return st;
+  size_t ws = 0;
+  if ((st = lp_workspace_size(job->dtype, job->n, job->d, job->offsets, job->m, job->k, &ws)) != LP_OK)
+    return st;
+  *bytes = round_up(ws, 256) + extra_bytes(job);
+  return LP_OK;
+}
+
+lp_status lp_server_create(lp_server** out, size_t hbm_budget_bytes, int32_t max_active) {
+  if (out == nullptr || max_active < 1 || max_active > 64 || hbm_budget_bytes == 0)
+    return lp::report(LP_EINVAL, "need out != NULL, 1 <= max_active <= 64, budget > 0");
+  lp_server* S = new lp_server();
+  S->budget = hbm_budget_bytes;
+  S->max_active = max_active;
+  if (hipGetDevice(&S->device) != hipSuccess ||
+      hipHostMalloc((void**)&S->pinned, sizeof(double) * max_active, hipHostMallocDefault) != hipSuccess) {
+    delete S;
+    return lp::report(LP_EDEVICE, "serving: device or pinned memory unavailable");
+  }
+  S->slot_stream.assign(max_active, nullptr);
+  S->slot_event.assign(max_active, nullptr);
+  for (int i = 0; i < max_active; ++i) {
+    if (hipStreamCreateWithFlags(&S->slot_stream[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->slot_event[i], hipEventDisableTiming) != hipSuccess) {
+      for (int t = 0; t <= i; ++t) {
+        if (S->slot_stream[t]) (void)hipStreamDestroy(S->slot_stream[t]);
+        if (S->slot_event[t]) (void)hipEventDestroy(S->slot_event[t]);
+      }
+      (void)hipHostFree(S->pinned);
+      delete S;
+      return lp::report(LP_EDEVICE, "serving: stream creation failed");
+    }
+    S->free_slots.push_back(max_active - 1 - i);
+  }
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return LP_OK;
+}
+
+lp_status lp_server_submit(lp_server* S, const lp_job* job, uint64_t* job_id) {
+  if (S == nullptr || job_id == nullptr) return lp::report(LP_EINVAL, "server or job_id is NULL");
+  size_t fp = 0;
+  lp_status st = lp_server_footprint(job, &fp);
+  if (st != LP_OK) return st;
+  if (fp > S->budget) return lp::report(LP_ENOMEM, "job footprint exceeds the server budget");
+  Job* j = new Job();
+  j->spec = *job;
+  j->offsets.assign(job->offsets, job->offsets + job->m + 1);
+  j->spec.offsets = nullptr;
+  j->y0.assign(job->Y0, job->Y0 + (size_t)job->d * job->k);
+  j->spec.Y0 = nullptr;
+  j->footprint = fp;
+  j->ws_bytes = fp - extra_bytes(job);
+  j->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->stopping) {
+      delete j;
+      return lp::report(LP_EBUSY, "server is stopping");
+    }
+    j->id = S->next_id++;
+    *job_id = j->id;
+    S->queue.push_back(j);
+  }
+  S->cv_work.notify_all();
+  return LP_OK;
+}
+
+lp_status lp_server_poll(lp_server* S, lp_job_result* out, int32_t max, int32_t* n_done) {
+  if (S == nullptr || n_done == nullptr || (max > 0 && out == nullptr)) return lp::report(LP_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(S->mu);
+  int n = 0;
+  while (n < max && !S->done.empty()) {
+    out[n++] = S->done.front();
+    S->done.pop_front();
+  }
+  *n_done = n;
+  return LP_OK;
+}
+
+lp_status lp_server_wait(lp_server* S, int32_t min_done, double timeout_s) {
+  if (S == nullptr) return lp::report(LP_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  const bool ok = S->cv_done.wait_for(lk, std::chrono::duration<double>(std::max(timeout_s, 0.0)),
+                                      [&] { return (int)S->done.size() >= min_done; });
+  return ok ? LP_OK : lp::report(LP_EBUSY, "timed out waiting for results");
+}
+
+lp_status lp_server_destroy(lp_server* S) {
+  if (S == nullptr) return LP_OK;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->stopping = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (int i = 0; i < S->max_active; ++i) {
+    (void)hipStreamSynchronize(S->slot_stream[i]);
+    (void)hipStreamDestroy(S->slot_stream[i]);
+    (void)hipEventDestroy(S->slot_event[i]);
+  }
+  (void)hipHostFree(S->pinned);
+  delete S;
+  return LP_OK;
+}
+
+}  // extern "C"
