@@ -129,12 +129,119 @@ def convergence(lp, P, w, k):
     return out
 
 
+def make_job_mix(n_jobs, seed, device):
+    """Seeded serving job list: d in {256, 512, 1024, 2048}, n = B d with B in
+    [16, 64], m in {4, 16}, FP32 (k in {4, 8, 16, 32}) or BF16 (k in {4, 8, 12}),
+    p0 = 4, target 1e-4; A low-rank-plus-noise with a gap of 1.5 at k, and the
+    exact top-k subspace of the stored A for the accuracy check."""
+    import synth
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for t in range(n_jobs):
+        d = int(rng.choice([256, 512, 1024, 2048]))
+        B = int(rng.integers(16, 65))
+        m = int(rng.choice([4, 16]))
+        bf16 = bool(rng.random() < 0.5)
+        k = int(rng.choice([4, 8, 12] if bf16 else [4, 8, 16, 32]))
+        mode = str(rng.choice(["sign", "opt"]))
+        w = synth.make_small(B * d, d, k, m, seed=seed * 100003 + t,
+                             dtype=torch.bfloat16 if bf16 else torch.float32, device=device, gap=1.5)
+        A64 = w.A.to(torch.float64)
+        _, V = torch.linalg.eigh(A64.T @ A64)
+        del A64
+        jobs.append((w, mode, V[:, -k:].contiguous()))
+    torch.cuda.synchronize()
+    return jobs
+
+
+def serve_run(lp, jobs, rate, max_active, budget, seed):
+    """Submit the jobs with Poisson arrivals at `rate` per second (all at once
+    when rate is 0), collect every result; returns throughput and latencies."""
+    S = lp.Server(hbm_budget_bytes=budget, max_active=max_active)
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, len(jobs)) if rate > 0 else np.zeros(len(jobs))
+    arrivals = np.cumsum(gaps)
+    ids = {}
+    results = []
+    t0 = time.perf_counter()
+    for (w, mode, U), at in zip(jobs, arrivals):
+        while time.perf_counter() - t0 < at:
+            results += S.poll()
+            time.sleep(0.0002)
+        ids[S.submit(w.A, w.offsets, w.k, w.Y0, p0=4, mode=mode, target=1e-4, max_rounds=300)] = (U, w)
+    while len(results) < len(jobs):
+        S.wait(len(jobs) - len(results), timeout_s=1.0)
+        results += S.poll()
+    el = time.perf_counter() - t0
+    S.close()
+    lat = np.array([r["ms_total"] for r in results])
+    worst = 0.0
+    ok = 0
+    errs = []
+    for r in results:
+        U, w = ids[r["id"]]
+        ok += r["status"] == 0
+        e = lp.lp_sin_theta(r["Z"], U)
+        worst = max(worst, e)
+        errs.append((e, {"d": w.d, "k": w.k, "m": w.m, "n": w.n, "dtype": str(w.A.dtype).split(".")[-1],
+                         "rounds": r["rounds"], "local_iters": r["local_iters"], "change": r["change"],
+                         "estimate": r["estimate"], "sin_theta_vs_truth": e}))
+    errs.sort(key=lambda x: -x[0])
+    return {"rate_per_s": rate if rate > 0 else "all at t=0", "max_active": max_active,
+            "jobs": len(jobs), "jobs_per_s": round(len(jobs) / el, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "converged": ok, "max_sin_theta_vs_truth": worst, "worst_jobs": [x[1] for x in errs[:3]],
+            "rounds_mean": round(float(np.mean([r["rounds"] for r in results])), 2)}
+
+
+def serve_main(args):
+    import paper_2002_08014_amd as lp
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n_jobs = args.jobs
+    log(f"generating {n_jobs} serving jobs")
+    jobs = make_job_mix(n_jobs, 4, dev)
+    total_bytes = sum(w.A.numel() * w.A.element_size() for w, _, _ in jobs)
+    budget = 64 << 30
+    runs = []
+    log("one job at a time, all submitted at t=0")
+    runs.append(serve_run(lp, jobs, 0, 1, budget, 1))
+    log("batched (16 active), all submitted at t=0")
+    runs.append(serve_run(lp, jobs, 0, 16, budget, 1))
+    for rate in args.rates:
+        log(f"batched (16 active), Poisson arrivals at {rate}/s")
+        runs.append(serve_run(lp, jobs, rate, 16, budget, 2))
+    best = runs[1]
+    out = {
+        "metric": METRIC,
+        "value": best["jobs_per_s"],
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "steps": len(runs),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {n_jobs} LocalPower jobs (d 256..2048, n = 16d..64d, "
+                               f"k 4..32, m 4/16, FP32 or BF16 A, p0 = 4 halved on stall, target 1e-4)",
+                   "A_bytes_total": int(total_bytes)},
+        "serving": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fp32-262144x1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fp32-262144x1024", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--jobs", type=int, default=120, help="serving: number of jobs")
+    ap.add_argument("--rates", type=float, nargs="*", default=[50.0, 200.0],
+                    help="serving: Poisson arrival rates (jobs/s)")
     ap.add_argument("--rounds", type=int, default=0, help="override the workload's round count")
     ap.add_argument("--mode", default=None, choices=["sign", "opt", "vanilla"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -144,6 +251,9 @@ def main():
         print(f"bench.py measures one GPU: the m LocalPower nodes are partitions on a single "
               f"device, so --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        serve_main(args)
+        return
     import synth
     import paper_2002_08014_amd as lp
 

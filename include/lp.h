@@ -227,15 +227,17 @@ lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, d
  *
  * Per-job schedule and stop rule.  The job starts from Z_0 = orth(Y0) with
  * p = p0 local steps per round.  After round r the change
- * c_r = sin theta_k(Z_r, Z_{r-1}) (Definition 1) is measured; with the
- * contraction ratio q = c_r / c_{r-1}:
- *   - the iterates have settled when c_r q / (1 - q) <= target with q < 1 (the
- *     tail of a geometric series of changes with ratio q, an estimate of the
- *     remaining distance to the limit of the current p), or when c_r == 0;
+ * c_r = sin theta_k(Z_r, Z_{r-1}) (Definition 1) is measured, and the ratio
+ * q_r = c_r / c_{r-1} over rounds run with the same p:
+ *   - with Q the larger of the last two such ratios, E = c_r Q / (1 - Q) (the
+ *     tail of a geometric series of changes, an estimate of the distance to
+ *     the limit of the current p); the iterates have settled when Q < 1 and
+ *     E <= target / 2 (a margin for the transient after p changes), or when
+ *     c_r == 0;
  *   - settled at p = 1, the job ends with LP_OK;
- *   - settled at p > 1, or a round with q > 0.5 (a stall), halves p: the limit
- *     of a fixed p > 1 sits at an error floor set by the heterogeneity of the
- *     partitions, and p = 1 has none (the decaying p of Sections 3 and 5);
+ *   - settled at p > 1, or q_r > 0.5 (a stall), halves p: the limit of a fixed
+ *     p > 1 sits at an error floor set by the heterogeneity of the partitions,
+ *     and p = 1 has none (the decaying p of Sections 3 and 5);
  *   - after max_rounds rounds the job ends with LP_ENOTCONV.
  * Z_out then holds the last iterate.  Results of a job do not depend on what
  * else the server runs (bitwise): every job has its own workspace and stream.
@@ -266,7 +268,7 @@ typedef struct {
   int32_t local_iters;     /* local steps run (sum of p over the rounds) */
   int32_t p_final;         /* p of the last round */
   double change;           /* last c_r */
-  double estimate;         /* last c_r q / (1 - q) (c_r when q >= 1 or r = 1) */
+  double estimate;         /* last E (c_r while fewer than two ratios exist or Q >= 1) */
   double ms_queued;        /* submission -> admission, host clock */
   double ms_total;         /* submission -> result published */
 } lp_job_result;

@@ -46,7 +46,7 @@ struct Job {
   double* change_dev = nullptr;
   // schedule state
   int p = 1, rounds = 0, iters = 0;
-  double prev_change = -1.0, change = 0.0, estimate = 0.0;
+  double prev_change = -1.0, prev_q = -1.0, change = 0.0, estimate = 0.0;
   bool in_flight = false;
 };
 
@@ -195,11 +195,15 @@ bool advance(lp_server* S, Job* j) {
   j->change = S->pinned[j->slot];
   j->rounds++;
   j->iters += j->p;
-  double q = 1.0;
-  if (j->prev_change > 0.0) q = j->change / j->prev_change;
-  j->estimate = (j->prev_change > 0.0 && q < 1.0) ? j->change * q / (1.0 - q) : j->change;
-  const bool settled =
-      j->change == 0.0 || (j->prev_change > 0.0 && q < 1.0 && j->estimate <= j->spec.target);
+  // contraction ratios of the changes at the current p; the estimate uses the
+  // larger of the last two (the first rounds after a change of p contract
+  // faster than the asymptotic rate and would underestimate the tail)
+  const double q = j->prev_change > 0.0 ? j->change / j->prev_change : -1.0;
+  const double qe = (q >= 0.0 && j->prev_q >= 0.0) ? std::max(q, j->prev_q) : -1.0;
+  const bool ratio = qe >= 0.0 && qe < 1.0;
+  j->estimate = ratio ? j->change * qe / (1.0 - qe) : j->change;
+  const bool settled = j->change == 0.0 || (ratio && j->estimate <= 0.5 * j->spec.target);
+  j->prev_q = q;
   j->prev_change = j->change;
   // settled at p = 1: done.  Settled at p > 1 only means the iterates reached
   // the fixed point of this p, which sits at an error floor: halve p.
@@ -211,7 +215,11 @@ bool advance(lp_server* S, Job* j) {
     finish(S, j, LP_ENOTCONV);
     return false;
   }
-  if (j->p > 1 && (settled || (j->rounds >= 2 && q > 0.5))) j->p = std::max(1, j->p / 2);
+  if (j->p > 1 && (settled || q > 0.5)) {
+    j->p = std::max(1, j->p / 2);
+    j->prev_change = -1.0;
+    j->prev_q = -1.0;
+  }
   lp_status st = launch(S, j);
   if (st != LP_OK) {
     finish(S, j, st);
