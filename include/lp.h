@@ -90,17 +90,22 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
 lp_status lp_destroy(lp_problem* P);
 
 /* Tuning of the local-multiply kernel (what the autotuner varies).
- *   local_kernel: 0 automatic; 1 generic two-pass kernel; 2..5 fused matrix-core kernel
- *                 with one workgroup per CU: 2 four waves; 3 eight waves; 4 software-
- *                 pipelined (two LDS tiles, product 2 of one tile interleaved with
+ *   local_kernel: 0 automatic; 1 two-pass kernel (t = A Z, then A^T t; FP32 matrix cores
+ *                 for FP32/BF16 A, FP64 arithmetic for FP64 A).  Fused matrix-core kernels
+ *                 (A read once), one workgroup per CU:
+ *                 FP32 A (k = 16, d in {256, 512, 768, 1024}): 2 four waves; 3 eight waves;
+ *                 4 software-pipelined (two LDS tiles, product 2 of one tile interleaved with
  *                 product 1 of the next), eight waves; 5 pipelined, four waves; 6 eight
- *                 waves with the next two tiles in flight (deeper prefetch).  The
- *                 eight-wave forms need d in {512, 1024} (else they run with four waves).
- *                 Fused variants need FP32 A, k = 16, d in {256, 512, 768, 1024}; other
- *                 runs use the two-pass kernel.
+ *                 waves with the next two tiles in flight (deeper prefetch); 7 direct-to-LDS
+ *                 tile loads (eight waves at d = 1024, else four); 8 direct-to-LDS, four
+ *                 waves.  The eight-wave forms need d in {512, 1024} (else they run with
+ *                 four waves).
+ *                 BF16 A (k in {16, 32}, d in {512, 1024, 1536, 2048}; Z and t rounded to
+ *                 BF16 as operands): 2 four waves; 3 eight waves (d in {1024, 2048}).
+ *                 Other shapes and ranks use the two-pass kernel.
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
  *                 default chosen at lp_create, which sized the workspace); 0 = default.
- *   cached_loads: 1 reads A with ordinary (cached) loads in the fused kernel; 0 (default)
+ *   cached_loads: 1 reads A with ordinary (cached) loads in the fused kernels; 0 (default)
  *                 with nontemporal loads, since A is streamed once per local iteration. */
 typedef struct {
   int32_t struct_size;

@@ -290,6 +290,196 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
     for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
 }
 
+// Direct-to-LDS form: each wave copies its own column slice of every tile
+// HBM -> LDS with global_load_lds_dwordx4 (no register staging, no barrier for
+// the tile), two tile buffers per wave, explicit vmcnt waits.  Inside a wave
+// row the 16-byte chunk c of tile row r sits at position
+//   c ^ ((r ^ (c >> 4)) & 15)
+// (the XOR stays inside the chunk's 256-byte group), which keeps the
+// product-1 pattern (16 rows, one chunk) and the product-2 pattern (one row,
+// chunks NQ/4 apart) free of bank conflicts.  Rows past the end of the item
+// repeat the last row; their t is zeroed.  Operand layouts as in
+// k1_mfma_f32_k16.  AUX: cache policy of the A loads (0, or 2 = nontemporal).
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ inline int dpos(int r, int c) { return c ^ ((r ^ (c >> 4)) & 15); }
+
+__device__ inline unsigned lds_addr(const void* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// Workgroup barrier for LDS data only: the LDS writes of this wave are complete
+// (lgkmcnt), then s_barrier.  __syncthreads() would also wait for every
+// outstanding global load, i.e. for the next tile's direct-to-LDS loads.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Four 128-bit LDS reads issued together and waited for inside the same asm
+// block.  Reads of the tile buffers go through these so that the compiler,
+// which cannot tell which buffer a pending direct-to-LDS load writes, does not
+// wait for the next tile's loads before reading the current tile.
+__device__ inline void lds_read4(f4& x0, f4& x1, f4& x2, f4& x3, unsigned a0, unsigned a1,
+                                 unsigned a2, unsigned a3) {
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %5\n\t"
+      "ds_read_b128 %2, %6\n\t"
+      "ds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+}
+
+// Wait for every outstanding global memory operation of this wave (the
+// direct-to-LDS loads included); also a compiler barrier.
+__device__ inline void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <int NQ, int W, int AUX>
+__global__ void __launch_bounds__(64 * W, 1)
+k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
+                int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+  constexpr int D = 16 * NQ * W;
+  constexpr int S = 16 * NQ;            // columns per wave slice
+  constexpr int RB = 4 * S;             // bytes per slice row
+  constexpr int TB = kTileRows * RB;    // bytes per wave tile
+  constexpr int NI = TB / 1024;         // 1 KB direct-to-LDS loads per wave tile
+  static_assert(NQ % 4 == 0 && TB % 1024 == 0, "slice rows must be whole 256-byte groups");
+  __shared__ __attribute__((aligned(16))) unsigned char abuf[2][W][TB];
+  __shared__ f4 tpart[W][64];
+
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane >> 4;
+  const int i = lane & 15;
+  const int slice0 = w * S;
+  const int rows = (int)it.rows;
+  const int ntiles = (rows + kTileRows - 1) / kTileRows;
+  const float* Ab = A + it.row0 * lda + slice0;
+
+  // Per-lane element offsets of the NI 1 KB loads of a tile (tile row * lda +
+  // column), fixed for the item; a full tile needs only the uniform tile base.
+  int32_t loff[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int byte = ii * 1024 + 16 * lane;
+    const int r = byte / RB;
+    const int p = (byte % RB) / 16;
+    loff[ii] = r * (int32_t)lda + 4 * (p ^ ((r ^ (p >> 4)) & 15));   // the chunk stored at position p
+  }
+  auto issue = [&](int r0, int b) {
+    if (r0 + kTileRows <= rows) {
+      const float* base = Ab + (int64_t)r0 * lda;
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii)
+        __builtin_amdgcn_global_load_lds((const void*)(base + loff[ii]),
+                                         (lds_void*)&abuf[b][w][ii * 1024], 16, 0, AUX);
+    } else {
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii) {
+        const int byte = ii * 1024 + 16 * lane;
+        const int r = byte / RB;
+        const int p = (byte % RB) / 16;
+        const int row = min(r0 + r, rows - 1);
+        const float* src = Ab + (int64_t)row * lda + 4 * (p ^ ((r ^ (p >> 4)) & 15));
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)&abuf[b][w][ii * 1024], 16, 0,
+                                         AUX);
+      }
+    }
+  };
+  issue(0, 0);
+
+  const float* Z = Zw + (int64_t)it.part * z_stride;
+  float zr[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+  f4 acc[NQ];
+#pragma unroll
+  for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int j = 0; j < ntiles; ++j) {
+    const int b = j & 1;
+    // tile j was issued one iteration ago: wait for it (a full wait, so no other
+    // memory operation the compiler placed in between can satisfy the count),
+    // then start tile j + 1 into the other buffer; it lands while tile j computes
+    wait_vm_all();
+    if (j + 1 < ntiles) issue((j + 1) * kTileRows, b ^ 1);
+    const unsigned tb = lds_addr(&abuf[b][w][0]);
+    unsigned ad1[NQ], ad2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ad1[q] = tb + i * RB + 16 * dpos(i, 4 * q + g);
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+      const int r = 4 * g + s;
+      ad2[st] = tb + r * RB + 16 * dpos(r, (NQ / 4) * i + cq);
+    }
+    f4 a1[NQ], a2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q += 4)
+      lds_read4(a1[q], a1[q + 1], a1[q + 2], a1[q + 3], ad1[q], ad1[q + 1], ad1[q + 2], ad1[q + 3]);
+#pragma unroll
+    for (int q = 0; q < NQ; q += 4)
+      lds_read4(a2[q], a2[q + 1], a2[q + 2], a2[q + 3], ad2[q], ad2[q + 1], ad2[q + 2], ad2[q + 3]);
+    f4 tw0 = f4{0.f, 0.f, 0.f, 0.f}, tw1 = tw0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      f4& tw = (q & 1) ? tw1 : tw0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        tw = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q][c], zr[q][c], tw, 0, 0, 0);
+    }
+    tpart[w][lane] = tw0 + tw1;
+    lds_barrier();
+    f4 t = tpart[0][lane];
+#pragma unroll
+    for (int v = 1; v < W; ++v) t += tpart[v][lane];
+    const int valid = rows - j * kTileRows;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * g + r >= valid) t[r] = 0.f;
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[4 * cq + c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[st][c], t[s], acc[4 * cq + c], 0, 0, 0);
+    }
+    lds_barrier();   // every wave has read tpart before the next tile overwrites it
+  }
+  float* o = part + (int64_t)it.slot * D * 16;
+#pragma unroll
+  for (int h = 0; h < NQ; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+}
+
+template <int NQ, int W, int AUX>
+hipError_t launch_dma_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
+                         const WorkItem* items, float* o, hipStream_t s) {
+  if constexpr (16 * NQ * W <= 1024 && NQ % 4 == 0) {
+    k1_mfma_f32_dma<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int W, int AUX>
+hipError_t launch_f32_dma(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
+                          int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+  switch (d / (16 * W)) {
+    case 4: return launch_dma_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 8: return launch_dma_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 12: return launch_dma_nq<12, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 16: return launch_dma_nq<16, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int NQ, int W, bool NT>
 hipError_t launch_pipe_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
                           const WorkItem* items, float* o, hipStream_t s) {
@@ -341,11 +531,12 @@ hipError_t launch_f32(int64_t d, int nitems, const float* a, int64_t lda, const 
 
 bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
   return dtype == LP_F32 && k == 16 && (d == 256 || d == 512 || d == 768 || d == 1024) &&
-         (lda % 4) == 0;
+         (lda % 4) == 0 && lda <= (int64_t(1) << 26);   // 32-bit in-tile load offsets
 }
 
 // Variants: 0: 4 waves, 1 WG/CU; 1: 8 waves, 1 WG/CU; 2: pipelined, 8 waves;
-// 3: pipelined, 4 waves; 4: 8 waves with two tiles in flight.  The 8-wave forms need d in {512, 1024} (else 4 waves).
+// 3: pipelined, 4 waves; 4: 8 waves with two tiles in flight; 5: direct-to-LDS tile
+// loads (8 waves at d = 1024, else 4); 6: direct-to-LDS, 4 waves.  The 8-wave forms need d in {512, 1024} (else 4 waves).
 template <bool NT>
 hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, const float* z,
                         int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
@@ -361,6 +552,18 @@ hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, 
     case 4:
       if (w8) return launch_f32<8, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
       return launch_f32<4, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    case 5: {
+      // direct-to-LDS form: 8 waves when the slice is a whole number of 256-byte
+      // groups (d = 512 gives 64-column slices: 4 waves), else 4 waves
+      constexpr int AUX = NT ? 2 : 0;
+      if (P.d == 1024) return launch_f32_dma<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    }
+    case 6: {
+      // direct-to-LDS form with four waves (one per SIMD, 512 registers each)
+      constexpr int AUX = NT ? 2 : 0;
+      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    }
     default: return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
   }
 }

@@ -35,7 +35,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(3))) s4 lds_s4;
 
 constexpr int kRows = 16;   // tile rows
 
@@ -46,16 +45,55 @@ __device__ inline uint16_t bf16_bits(float x) {
   return __builtin_bit_cast(uint16_t, h);
 }
 
-// Wait until at most N direct-to-LDS loads of this wave are outstanding; also a
-// compiler barrier, so no LDS read is moved above it.
-template <int N>
-__device__ inline void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  if constexpr (N == 0)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  else
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned lds_addr(const void* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
+
+// Workgroup barrier for LDS data only: the LDS writes of this wave are complete
+// (lgkmcnt), then s_barrier.  __syncthreads() would also wait for every
+// outstanding global load, i.e. for the next tile's direct-to-LDS loads.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Tile-buffer reads, issued together and waited for inside the same asm block:
+// the compiler cannot tell which buffer a pending direct-to-LDS load writes and
+// would otherwise wait for the next tile's loads before reading this one.
+__device__ inline void lds_read4_b128(bf8& x0, bf8& x1, bf8& x2, bf8& x3, unsigned a0, unsigned a1,
+                                      unsigned a2, unsigned a3) {
+  f4v y0, y1, y2, y3;
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %5\n\t"
+      "ds_read_b128 %2, %6\n\t"
+      "ds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+  x0 = __builtin_bit_cast(bf8, y0);
+  x1 = __builtin_bit_cast(bf8, y1);
+  x2 = __builtin_bit_cast(bf8, y2);
+  x3 = __builtin_bit_cast(bf8, y3);
+}
+
+// Four transposing 64-bit reads (ds_read_b64_tr_b16, semantics in the header).
+__device__ inline void lds_read4_tr(s4& x0, s4& x1, s4& x2, s4& x3, unsigned a0, unsigned a1,
+                                    unsigned a2, unsigned a3) {
+  asm volatile(
+      "ds_read_b64_tr_b16 %0, %4\n\t"
+      "ds_read_b64_tr_b16 %1, %5\n\t"
+      "ds_read_b64_tr_b16 %2, %6\n\t"
+      "ds_read_b64_tr_b16 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+}
+
+// Wait for every outstanding global memory operation of this wave (the
+// direct-to-LDS loads included); also a compiler barrier.
+__device__ inline void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // W: waves; NC: 32-column chunks per wave slice (d = 32 NC W); KT: 16-wide k
 // blocks (k = 16 KT); AUX: cache policy of the A loads (0 default, 2 nontemporal).
@@ -86,16 +124,15 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
   const int ntiles = (rows + kRows - 1) / kRows;
   const uint16_t* Ab = A + it.row0 * lda + slice0;
 
-  // start the first tile before anything else
+  // Rows past the end of the item repeat the last row (their t is zeroed).
   auto issue = [&](int r0, int b) {
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
       const int byte = ii * 1024 + 16 * lane;
       const int r = byte / RB;
       const int p = (byte % RB) / 16;
-      const int gc = p ^ bswz(r);
-      const int row = min(r0 + r, rows - 1);   // rows past the item repeat the last one; their t is zeroed
-      const uint16_t* src = Ab + (int64_t)row * lda + 8 * gc;
+      const int row = min(r0 + r, rows - 1);
+      const uint16_t* src = Ab + (int64_t)row * lda + 8 * (p ^ bswz(r));
       __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)&abuf[b][w][ii * 1024], 16, 0, AUX);
     }
   };
@@ -131,13 +168,12 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
 
   for (int j = 0; j < ntiles; ++j) {
     const int b = j & 1;
-    if (j + 1 < ntiles) {
-      issue((j + 1) * kRows, b ^ 1);
-      wait_vm<NI>();
-    } else {
-      wait_vm<0>();
-    }
-    const unsigned char* tb = &abuf[b][w][0];
+    // tile j was issued one iteration ago: wait for it (a full wait, so no other
+    // memory operation the compiler placed in between can satisfy the count),
+    // then start tile j + 1 into the other buffer; it lands while tile j computes
+    wait_vm_all();
+    if (j + 1 < ntiles) issue((j + 1) * kRows, b ^ 1);
+    const unsigned tb = lds_addr(&abuf[b][w][0]);
 
     // product 1: partial t over this wave's slice (two chains per k block)
     f4 tacc[KT][2];
@@ -146,8 +182,9 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
     for (int c0 = 0; c0 < NC; c0 += 4) {
       bf8 a1[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a1[c] = *(const bf8*)(tb + 256 * (c0 / 4) + off1[c]);
+      const unsigned base1 = tb + 256 * (c0 / 4);
+      lds_read4_b128(a1[0], a1[1], a1[2], a1[3], base1 + off1[0], base1 + off1[1], base1 + off1[2],
+                     base1 + off1[3]);
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -157,7 +194,7 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     }
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) tpart[w][kt][lane] = tacc[kt][0] + tacc[kt][1];
-    __syncthreads();
+    lds_barrier();
 
     // sum the W slice partials (fixed order), round to BF16, store t^T;
     // rows past the end of the item get t = 0
@@ -172,7 +209,7 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
       const int row = 4 * g + r;
       tbf[(i + 16 * kt) * kRows + row] = bf16_bits(row < valid ? s : 0.f);
     }
-    __syncthreads();
+    lds_barrier();
 
     // product 2: Y_slice += A_tile^T t
     s4 tb_op[KT];
@@ -181,10 +218,11 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
     for (int c0 = 0; c0 < NCT; c0 += 8) {
       s4 a2[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        a2[c] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-            (lds_s4*)(tb + 256 * (c0 / 8) + off2[c]));
+      const unsigned base2 = tb + 256 * (c0 / 8);
+      lds_read4_tr(a2[0], a2[1], a2[2], a2[3], base2 + off2[0], base2 + off2[1], base2 + off2[2],
+                   base2 + off2[3]);
+      lds_read4_tr(a2[4], a2[5], a2[6], a2[7], base2 + off2[4], base2 + off2[5], base2 + off2[6],
+                   base2 + off2[7]);
 #pragma unroll
       for (int c = 0; c < 8; ++c)
 #pragma unroll

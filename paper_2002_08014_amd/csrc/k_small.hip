@@ -15,6 +15,16 @@ namespace {
 // owns the entries (ty + 16a, tx + 16c), a, c < KC.  Needs kBlock threads.
 template <int KC>
 __device__ void gram_tile(const double* Xs, const double* Ws, int rows, int k, double* out) {
+  if constexpr (KC == 1) {
+    // k <= 16: one entry per thread, the plain loop is the fastest form
+    for (int e = threadIdx.x; e < k * k; e += kBlock) {
+      const int i = e / k, j = e - (e / k) * k;
+      double s = 0.0;
+      for (int r = 0; r < rows; ++r) s = fma(Xs[r * k + i], Ws[r * k + j], s);
+      out[e] = s;
+    }
+    return;
+  }
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   double acc[KC][KC];
 #pragma unroll

@@ -588,7 +588,7 @@ lp_status lp_destroy(lp_problem* P) {
 lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
     return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
-  if (t->local_kernel < 0 || t->local_kernel > 6) return fail(LP_EINVAL, "local_kernel out of range");
+  if (t->local_kernel < 0 || t->local_kernel > 8) return fail(LP_EINVAL, "local_kernel out of range");
   if (t->local_kernel > 3 && fused_kind(P) == LocalPath::MfmaBf16)
     return fail(LP_EINVAL, "the BF16 fused kernel has two variants (local_kernel 2, 3)");
   int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
@@ -689,7 +689,7 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
     return LP_OK;
   }
   const bool fused_ok = fused_for_k(P, k);
-  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 6 : 3;
+  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 8 : 3;
   std::vector<lp_tuning> cand;
   const int64_t c0 = P->plan.min_chunk_rows;
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
@@ -706,26 +706,44 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
   hipEvent_t e0, e1;
   LP_HIP(hipEventCreate(&e0));
   LP_HIP(hipEventCreate(&e1));
-  double best_ms = 1e300;
-  for (const lp_tuning& c : cand) {
-    if ((st = lp_set_tuning(P, &c)) != LP_OK) break;
-    hipError_t e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part,
-                                         q.items, P->stream);
+  // average time of `reps` launches of candidate c after two untimed ones
+  auto time_candidate = [&](const lp_tuning& c, int reps, double* ms_out) -> lp_status {
+    lp_status cs = lp_set_tuning(P, &c);
+    if (cs != LP_OK) return cs;
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < 2 && e == hipSuccess; ++it)
+      e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
+                                P->stream);
     if (e == hipSuccess) e = hipEventRecord(e0, P->stream);
-    for (int it = 0; it < 3 && e == hipSuccess; ++it)
+    for (int it = 0; it < reps && e == hipSuccess; ++it)
       e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
                                 P->stream);
     if (e == hipSuccess) e = hipEventRecord(e1, P->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      st = fail(LP_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
-      break;
-    }
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+    if (e != hipSuccess) return fail(LP_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    *ms_out = ms / reps;
+    return LP_OK;
+  };
+  // bring the clocks up before anything is compared
+  double ms = 0.0;
+  st = time_candidate(cand[0], 24, &ms);
+  // first pass over every candidate, then the three fastest again
+  std::vector<std::pair<double, size_t>> order;
+  for (size_t ci = 0; ci < cand.size() && st == LP_OK; ++ci) {
+    st = time_candidate(cand[ci], 6, &ms);
+    order.emplace_back(ms, ci);
+  }
+  double best_ms = 1e300;
+  if (st == LP_OK) {
+    std::sort(order.begin(), order.end());
+    for (size_t r = 0; r < std::min<size_t>(3, order.size()) && st == LP_OK; ++r) {
+      st = time_candidate(cand[order[r].second], 12, &ms);
+      if (st == LP_OK && ms < best_ms) {
+        best_ms = ms;
+        best = cand[order[r].second];
+      }
     }
   }
   (void)hipEventDestroy(e0);
