@@ -16,12 +16,30 @@ namespace {
 template <int KC>
 __device__ void gram_tile(const double* Xs, const double* Ws, int rows, int k, double* out) {
   if constexpr (KC == 1) {
-    // k <= 16: one entry per thread, the plain loop is the fastest form
+    // k <= 16: FP64 matrix cores.  v_mfma_f64_16x16x4f64 with A[i][q] = X[r + q][i] and
+    // B[q][j] = W[r + q][j] (lane l supplies row r + l/16, column l%16 of each, zero
+    // past k and past `rows`); wave w sums rows 4s (s = w, w + 4, ...), and the four
+    // wave sums are added in a fixed order through LDS.
+    __shared__ double gsum[4][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = lane & 15, q = lane >> 4;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 4 * w; r < rows; r += 16) {
+      const int rr = r + q;
+      const bool ok = rr < rows && c < k;
+      const double a = ok ? Xs[rr * k + c] : 0.0;
+      const double b = ok ? Ws[rr * k + c] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    // the FP64 16x16x4 result interleaves rows: lane l holds entries (4t + l/16, l%16), t < 4
+    // (measured on gfx950; the FP32 16x16x4 form holds rows 4(l/16) + t instead)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) gsum[w][(4 * t + q) * 16 + c] = acc[t];
+    __syncthreads();
     for (int e = threadIdx.x; e < k * k; e += kBlock) {
       const int i = e / k, j = e - (e / k) * k;
-      double s = 0.0;
-      for (int r = 0; r < rows; ++r) s = fma(Xs[r * k + i], Ws[r * k + j], s);
-      out[e] = s;
+      out[e] = ((gsum[0][i * 16 + j] + gsum[1][i * 16 + j]) + gsum[2][i * 16 + j]) + gsum[3][i * 16 + j];
     }
     return;
   }
