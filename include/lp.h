@@ -196,8 +196,10 @@ lp_status lp_orth(lp_problem* P, int32_t k, int32_t batch, const double* Y, doub
 /* Alignment of batch iterates Zi (device, batch x d x k FP64) against Zb (device
  * d x k FP64):
  *   LP_AGG_SIGN: out is device int8[batch*k], sgn(<Zi[:,j], Zb[:,j]>) with sgn(0)=+1;
- *   LP_AGG_OPT : out is device FP64 [batch*k*k], O_i = W1 W2^T from the SVD
- *                W1 S W2^T = Zi^T Zb (one-sided Jacobi, FP64).
+ *   LP_AGG_OPT : out is device FP64 [batch*k*k], O_i = W1 W2^T for the SVD
+ *                W1 S W2^T = Zi^T Zb, computed as the orthogonal polar factor of
+ *                Zi^T Zb by Newton-Schulz iteration in FP64 (the same matrix when
+ *                Zi^T Zb is nonsingular).
  * Same workspace/stream rules as lp_orth. */
 lp_status lp_align(lp_problem* P, int32_t k, int32_t batch, lp_agg mode, const double* Zi,
                    const double* Zb, void* out);

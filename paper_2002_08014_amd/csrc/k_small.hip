@@ -642,91 +642,90 @@ __device__ void jacobi_sym_lds(double* S, double* V, int k, double* cs, double* 
 }
 
 // ---------------------------------------------------------------------------
-// Orthogonal Procrustes O = W1 W2^T of C = W1 S W2^T (one-sided Jacobi); grid (batch)
+// Orthogonal Procrustes factor O_b = W1 W2^T of C_b = Z_b_i^T Z_base (Eq. (opt:o)),
+// i.e. the orthogonal polar factor C (C^T C)^{-1/2}: one workgroup per matrix,
+// Newton-Schulz iteration X <- X (3I - X^T X) / 2 from X_0 = C / s, s =
+// sqrt(max row sum of |C^T C|) >= sigma_max(C), which converges (quadratically
+// at the end) for every nonsingular C; it stops one iteration after
+// max|X^T X - I| <= 1e-13.  A C that does not converge within the cap (singular
+// or nearly so, where O is not unique) sets flags[b].  grid (batch)
 // ---------------------------------------------------------------------------
+template <int KC>
 __global__ void __launch_bounds__(kBlock)
-procrustes_kernel(int nchunks, int k, const double* part, double* O,
-                  int32_t* __restrict__ flags) {
+polar_kernel(int nchunks, int k, const double* part, double* O, int32_t* flags) {
   __shared__ double X[kMaxK * kMaxK];
-  __shared__ double V[kMaxK * kMaxK];
-  __shared__ double nrm[kMaxK];
-  __shared__ int rotated;
+  __shared__ double A[kMaxK * kMaxK];
+  __shared__ double red[kMaxK];
+  __shared__ int off;
   const int b = blockIdx.x;
+  const int kk = k * k;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   sum_partials(part, b, nchunks, k, X);
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) V[e] = (e / k == e % k) ? 1.0 : 0.0;
-  const int kk = k + (k & 1);
-  const int npairs = kk / 2;
-  // threads per pair: a power of two within one wavefront
-  int g = 64;
-  while (g > 1 && g * npairs > kBlock) g >>= 1;
-  const int pair = threadIdx.x / g;
-  const int lane = threadIdx.x % g;
   __syncthreads();
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
+  // scale: s^2 = max_i sum_j |(C^T C)_ij|
+  gram_tile<KC>(X, X, k, k, A);
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += kBlock) {
+    double rs = 0.0;
+    for (int j = 0; j < k; ++j) rs += fabs(A[i * k + j]);
+    red[i] = rs;
+  }
+  __syncthreads();
+  double s2 = 0.0;
+  for (int i = 0; i < k; ++i) s2 = fmax(s2, red[i]);
+  const double inv_s = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kk; e += kBlock) X[e] *= inv_s;
+  __syncthreads();
+  bool converged = false;
+  int extra = -1;   // iterations still to run after convergence
+  for (int it = 0; it < 120; ++it) {
+    gram_tile<KC>(X, X, k, k, A);     // A = X^T X
+    if (threadIdx.x == 0) off = 0;
     __syncthreads();
-    for (int st = 0; st < kk - 1; ++st) {
-      if (pair < npairs) {
-        int p, q;
-        rr_pair(kk, st, pair, &p, &q);
-        if (q < k) {
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int r = lane; r < k; r += g) {
-            const double xp = X[r * k + p], xq = X[r * k + q];
-            al += xp * xp;
-            be += xq * xq;
-            ga += xp * xq;
-          }
-          for (int o = g / 2; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o, g);
-            be += __shfl_xor(be, o, g);
-            ga += __shfl_xor(ga, o, g);
-          }
-          if (fabs(ga) > 1e-15 * sqrt(al * be) && ga != 0.0) {
-            double c, s;
-            sym_schur2(al, be, ga, &c, &s);
-            for (int r = lane; r < k; r += g) {
-              const double xp = X[r * k + p], xq = X[r * k + q];
-              X[r * k + p] = c * xp - s * xq;
-              X[r * k + q] = s * xp + c * xq;
-              const double vp = V[r * k + p], vq = V[r * k + q];
-              V[r * k + p] = c * vp - s * vq;
-              V[r * k + q] = s * vp + c * vq;
-            }
-            if (lane == 0) rotated = 1;
-          }
-        }
+    if (extra < 0) {
+      for (int e = threadIdx.x; e < kk; e += kBlock) {
+        const double dv = A[e] - ((e / k == e % k) ? 1.0 : 0.0);
+        if (!(fabs(dv) <= 1e-13)) off = 1;   // benign race: every writer stores 1
       }
       __syncthreads();
+      if (off == 0) extra = 1;
     }
-    if (!rotated) break;
+    if (extra == 0) {
+      converged = true;
+      break;
+    }
+    if (extra > 0) --extra;
+    // X <- 1.5 X - 0.5 X A
+    double acc[KC][KC];
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc[a][c] = 0.0;
+    for (int l = 0; l < k; ++l) {
+      double xv[KC], av[KC];
+#pragma unroll
+      for (int a = 0; a < KC; ++a) xv[a] = (ty + 16 * a < k) ? X[(ty + 16 * a) * k + l] : 0.0;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) av[c] = (tx + 16 * c < k) ? A[l * k + tx + 16 * c] : 0.0;
+#pragma unroll
+      for (int a = 0; a < KC; ++a)
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc[a][c] = fma(xv[a], av[c], acc[a][c]);
+    }
+    __syncthreads();   // every thread has read X
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const int i = ty + 16 * a, j = tx + 16 * c;
+        if (i < k && j < k) X[i * k + j] = 1.5 * X[i * k + j] - 0.5 * acc[a][c];
+      }
     __syncthreads();
   }
-  // singular values = column norms; W1 = X diag(1/sigma); O = W1 V^T
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < k; ++r) s += X[r * k + j] * X[r * k + j];
-    nrm[j] = sqrt(s);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && flags != nullptr) {
-    double mx = 0.0, mn = 1e300;
-    for (int j = 0; j < k; ++j) {
-      mx = fmax(mx, nrm[j]);
-      mn = fmin(mn, nrm[j]);
-    }
-    if (!(mn > 1e-12 * mx)) flags[b] = 1;
-  }
-  double* Ob = O + (int64_t)b * k * k;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    const int i = e / k, j = e - (e / k) * k;
-    double s = 0.0;
-    for (int l = 0; l < k; ++l) {
-      const double u = (nrm[l] > 0.0) ? X[i * k + l] / nrm[l] : 0.0;
-      s += u * V[j * k + l];
-    }
-    Ob[e] = s;
-  }
+  if (threadIdx.x == 0 && flags != nullptr && (!converged || s2 == 0.0)) flags[b] = 1;
+  double* Ob = O + (int64_t)b * kk;
+  for (int e = threadIdx.x; e < kk; e += kBlock) Ob[e] = X[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -914,15 +913,22 @@ hipError_t launch_sign_from_gram(int batch, int nchunks, int k, const double* gr
 
 hipError_t launch_procrustes(int batch, int nchunks, int k, const double* gram_part, double* O,
                              int32_t* flags, hipStream_t s) {
+  const double* src = gram_part;
+  int nch = nchunks;
   if (k > 16 && nchunks > 1) {
     // sum the partials with a wide launch into O (the kernel reads O[b] in full
     // before it writes O[b])
     sum_gram_kernel<<<dim3(nblk((int64_t)k * k, kBlock), batch), kBlock, 0, s>>>(nchunks, k * k,
                                                                                gram_part, O);
-    procrustes_kernel<<<batch, kBlock, 0, s>>>(1, k, O, O, flags);
-  } else {
-    procrustes_kernel<<<batch, kBlock, 0, s>>>(nchunks, k, gram_part, O, flags);
+    src = O;
+    nch = 1;
   }
+  if (k <= 16)
+    polar_kernel<1><<<batch, kBlock, 0, s>>>(nch, k, src, O, flags);
+  else if (k <= 32)
+    polar_kernel<2><<<batch, kBlock, 0, s>>>(nch, k, src, O, flags);
+  else
+    polar_kernel<4><<<batch, kBlock, 0, s>>>(nch, k, src, O, flags);
   return hipGetLastError();
 }
 

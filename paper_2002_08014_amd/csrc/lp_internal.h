@@ -181,7 +181,8 @@ hipError_t launch_sign_from_gram(int batch, int nchunks, int k, const double* gr
                                  int8_t* sgn, hipStream_t s);
 
 
-// Procrustes factor O_b = W1 W2^T of C_b = sum of cross-gram partials (one-sided Jacobi).
+// Procrustes factor O_b = W1 W2^T of C_b = sum of cross-gram partials (the orthogonal
+// polar factor of C_b, by Newton-Schulz iteration in FP64).
 hipError_t launch_procrustes(int batch, int nchunks, int k, const double* gram_part,
                              double* O, int32_t* flags, hipStream_t s);
 
