@@ -215,9 +215,8 @@ ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
 
 template <typename TA, int NT>
 hipError_t gemm_pair(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
-                     int64_t z_stride, void* tbuf, void* part, const WorkItem* items,
+                     int64_t z_stride, void* tbuf, void* part, const WorkItem* items, int nitems,
                      hipStream_t s) {
-  const int nitems = (int)P.items.size();
   dim3 g1(nitems, (unsigned)((P.chunk_rows + kBM - 1) / kBM));
   tmm_kernel<TA, NT><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)Zw, z_stride, items,
                                         (float*)tbuf);
@@ -231,11 +230,11 @@ hipError_t gemm_pair(const Plan& P, const void* A, int64_t lda, int k, const voi
 
 template <typename TA>
 hipError_t gemm_k(const Plan& P, const void* A, int64_t lda, int k, const void* Zw, int64_t z_stride,
-                  void* tbuf, void* part, const WorkItem* items, hipStream_t s) {
-  if (k <= 16) return gemm_pair<TA, 1>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  if (k <= 32) return gemm_pair<TA, 2>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  if (k <= 48) return gemm_pair<TA, 3>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  return gemm_pair<TA, 4>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+                  void* tbuf, void* part, const WorkItem* items, int nitems, hipStream_t s) {
+  if (k <= 16) return gemm_pair<TA, 1>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  if (k <= 32) return gemm_pair<TA, 2>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  if (k <= 48) return gemm_pair<TA, 3>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  return gemm_pair<TA, 4>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
 }
 
 }  // namespace
@@ -248,9 +247,11 @@ bool gemm_eligible(lp_dtype dtype, int64_t d, int64_t lda, const void* A) {
 
 hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
-                                      const WorkItem* items, hipStream_t s) {
-  if (P.dtype == LP_F32) return gemm_k<float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  return gemm_k<__hip_bfloat16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+                                      const WorkItem* items, int nitems,
+                                      hipStream_t s) {
+  if (P.dtype == LP_F32)
+    return gemm_k<float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  return gemm_k<__hip_bfloat16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
 }
 
 }  // namespace lp

@@ -121,9 +121,8 @@ __global__ void reduce_partials_kernel(int64_t dk, const TC* __restrict__ part,
 
 template <typename TA, typename TC, int KB>
 hipError_t two_pass(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
-                    int64_t z_stride, void* tbuf, void* part, const WorkItem* items,
+                    int64_t z_stride, void* tbuf, void* part, const WorkItem* items, int nitems,
                     hipStream_t s) {
-  const int nitems = (int)P.items.size();
   dim3 g1(nitems, (unsigned)((P.chunk_rows + 3) / 4));
   tpass_kernel<TA, TC, KB><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const TC*)Zw, z_stride,
                                               items, (TC*)tbuf);
@@ -137,26 +136,28 @@ hipError_t two_pass(const Plan& P, const void* A, int64_t lda, int k, const void
 
 template <typename TA, typename TC>
 hipError_t two_pass_k(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
-                      int64_t z_stride, void* tbuf, void* part, const WorkItem* items,
+                      int64_t z_stride, void* tbuf, void* part, const WorkItem* items, int n,
                       hipStream_t s) {
-  if (k <= 8) return two_pass<TA, TC, 8>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  if (k <= 16) return two_pass<TA, TC, 16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  if (k <= 32) return two_pass<TA, TC, 32>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
-  return two_pass<TA, TC, 64>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+  if (k <= 8) return two_pass<TA, TC, 8>(P, A, lda, k, Zw, z_stride, tbuf, part, items, n, s);
+  if (k <= 16) return two_pass<TA, TC, 16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, n, s);
+  if (k <= 32) return two_pass<TA, TC, 32>(P, A, lda, k, Zw, z_stride, tbuf, part, items, n, s);
+  return two_pass<TA, TC, 64>(P, A, lda, k, Zw, z_stride, tbuf, part, items, n, s);
 }
 
 }  // namespace
 
 hipError_t launch_local_multiply_twopass(const Plan& P, const void* A, int64_t lda, int k,
                                          const void* Zw, int64_t z_stride, void* tbuf, void* part,
-                                         const WorkItem* items, hipStream_t s) {
+                                         const WorkItem* items, int nitems,
+                                         hipStream_t s) {
   switch (P.dtype) {
     case LP_F64:
-      return two_pass_k<double, double>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+      return two_pass_k<double, double>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
     case LP_F32:
-      return two_pass_k<float, float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+      return two_pass_k<float, float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
     default:
-      return two_pass_k<__hip_bfloat16, float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, s);
+      return two_pass_k<__hip_bfloat16, float>(P, A, lda, k, Zw, z_stride, tbuf, part, items,
+                                               nitems, s);
   }
 }
 

@@ -570,8 +570,8 @@ hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, 
 
 hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
-                                        const WorkItem* items, hipStream_t s) {
-  const int nitems = (int)P.items.size();
+                                        const WorkItem* items, int nitems,
+                                        hipStream_t s) {
   const float* a = (const float*)A;
   const float* z = (const float*)Zw;
   float* o = (float*)part;

@@ -278,8 +278,8 @@ bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* 
 
 hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
-                                        const WorkItem* items, hipStream_t s) {
-  const int nitems = (int)P.items.size();
+                                        const WorkItem* items, int nitems,
+                                        hipStream_t s) {
   const uint16_t* a = (const uint16_t*)A;
   const float* z = (const float*)Zw;
   float* o = (float*)part;

@@ -43,28 +43,29 @@ __device__ void gram_tile(const double* Xs, const double* Ws, int rows, int k, d
     }
     return;
   }
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double acc[KC][KC];
+  // k > 16: FP64 matrix cores, one 16 x 16 output block (bi, bj) at a time per
+  // wave (blocks bi * KC + bj = w, w + 4, ...), K = rows in steps of 4:
+  // A[i][q] = X[r + q][16 bi + i], B[q][j] = W[r + q][16 bj + j]
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = lane & 15, q = lane >> 4;
+  for (int blk = w; blk < KC * KC; blk += 4) {
+    const int bi = blk / KC, bj = blk - (blk / KC) * KC;
+    const int ci = 16 * bi + c, cj = 16 * bj + c;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < rows; r += 4) {
+      const int rr = r + q;
+      const double a = (rr < rows && ci < k) ? Xs[rr * k + ci] : 0.0;
+      const double b = (rr < rows && cj < k) ? Ws[rr * k + cj] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    // lane l holds entries (16 bi + 4t + l/16, 16 bj + l%16)
 #pragma unroll
-  for (int a = 0; a < KC; ++a)
-#pragma unroll
-    for (int c = 0; c < KC; ++c) acc[a][c] = 0.0;
-  for (int r = 0; r < rows; ++r) {
-    double xi[KC], wj[KC];
-#pragma unroll
-    for (int a = 0; a < KC; ++a) xi[a] = (ty + 16 * a < k) ? Xs[r * k + ty + 16 * a] : 0.0;
-#pragma unroll
-    for (int c = 0; c < KC; ++c) wj[c] = (tx + 16 * c < k) ? Ws[r * k + tx + 16 * c] : 0.0;
-#pragma unroll
-    for (int a = 0; a < KC; ++a)
-#pragma unroll
-      for (int c = 0; c < KC; ++c) acc[a][c] = fma(xi[a], wj[c], acc[a][c]);
+    for (int t = 0; t < 4; ++t) {
+      const int i = 16 * bi + 4 * t + q, j = cj;
+      if (i < k && j < k) out[i * k + j] = acc[t];
+    }
   }
-#pragma unroll
-  for (int a = 0; a < KC; ++a)
-#pragma unroll
-    for (int c = 0; c < KC; ++c)
-      if (ty + 16 * a < k && tx + 16 * c < k) out[(ty + 16 * a) * k + tx + 16 * c] = acc[a][c];
 }
 
 // 16-column blocks needed for k columns
@@ -254,6 +255,38 @@ chol_inv_wave_kernel(int nch, int k, const double* __restrict__ gin, double* __r
   if (threadIdx.x == 0 && bad && flags != nullptr) flags[b] = 1;
 }
 
+// Rows [0, rows) of Xs (row stride k) times the k x k matrix S (LDS, row stride
+// k) on FP64 matrix cores, for a tile of at most 64 rows: wave w owns rows
+// 16w..16w+15 and all KC 16-column blocks; K = k in steps of 4 with
+// A[i][q] = X[16w + i][l + q], B[q][j] = S[l + q][16 bj + j] (S zero below the
+// diagonal when `upper`).  Returns the accumulators: lane l, block bj, t holds
+// the entry (16w + 4t + l/16, 16 bj + l%16).
+template <int KC>
+__device__ inline void tile_times_s(const double* Xs, const double* S, int rows, int k, bool upper,
+                                    double (&res)[KC][4]) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = lane & 15, q = lane >> 4;
+  const int row = 16 * w + c;
+  d4 acc[KC];
+#pragma unroll
+  for (int bj = 0; bj < KC; ++bj) acc[bj] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int l = 0; l < k; l += 4) {
+    const int lq = l + q;
+    const double a = (row < rows && lq < k) ? Xs[row * k + lq] : 0.0;
+#pragma unroll
+    for (int bj = 0; bj < KC; ++bj) {
+      const int j = 16 * bj + c;
+      const double b = (lq < k && j < k && (!upper || lq <= j)) ? S[lq * k + j] : 0.0;
+      acc[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[bj], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int bj = 0; bj < KC; ++bj)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) res[bj][t] = acc[bj][t];
+}
+
 // grid (ceil(d / 64), batch): Q = X R^{-1} for the 64-row chunk c of matrix b
 // (R^{-1} upper triangular, from rinv), the optional working copy, and the
 // optional Gram partial of the chunk's rows of Q (partial index b * gridDim.x + c).
@@ -272,41 +305,22 @@ apply_gram_kernel(int64_t d, int k, const double* __restrict__ X, const double* 
   for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rinv[(int64_t)b * k * k + e];
   for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = X[base + e];
   __syncthreads();
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double acc[4][KC];
+  double res[KC][4];
+  tile_times_s<KC>(Xs, Ri, rows, k, true, res);
+  __syncthreads();   // every wave has read Xs; it now holds the chunk of Q
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int bj = 0; bj < KC; ++bj)
 #pragma unroll
-    for (int cc = 0; cc < KC; ++cc) acc[a][cc] = 0.0;
-  for (int l = 0; l < k; ++l) {
-    double xv[4], sv[KC];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) xv[a] = (ty + 16 * a < rows) ? Xs[(ty + 16 * a) * k + l] : 0.0;
-#pragma unroll
-    for (int cc = 0; cc < KC; ++cc) {
-      const int j = tx + 16 * cc;
-      sv[cc] = (j < k && l <= j) ? Ri[l * k + j] : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int cc = 0; cc < KC; ++cc) acc[a][cc] = fma(xv[a], sv[cc], acc[a][cc]);
-  }
-  __syncthreads();   // every thread has read Xs; it now holds the chunk of Q
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int r = ty + 16 * a;
-#pragma unroll
-    for (int cc = 0; cc < KC; ++cc) {
-      const int j = tx + 16 * cc;
+    for (int t = 0; t < 4; ++t) {
+      const int r = 16 * w + 4 * t + (lane >> 4), j = 16 * bj + (lane & 15);
       if (r < rows && j < k) {
-        const double v = acc[a][cc];
+        const double v = res[bj][t];
         Q[base + (int64_t)r * k + j] = v;
         if (zw != nullptr) zw[base + (int64_t)r * k + j] = (TW)v;
         Xs[r * k + j] = v;
       }
     }
-  }
   if (gout != nullptr) {
     __syncthreads();
     gram_tile<KC>(Xs, Xs, rows, k, gout + ((int64_t)b * nch + c) * k * k);
@@ -468,12 +482,11 @@ sign_apply_kernel(int64_t d, int k, const double* __restrict__ part, double* __r
 // ---------------------------------------------------------------------------
 // Q_b = X_b S_b (S upper triangular when `upper`); grid (ceil(d / 64), batch)
 // ---------------------------------------------------------------------------
-template <typename TW>
+template <typename TW, int KC>
 __global__ void __launch_bounds__(kBlock)
 right_mult_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ S,
                   int64_t s_stride, int upper, double* __restrict__ Q, TW* __restrict__ zw) {
-  // 64-row tile of X and S staged in LDS; thread (ty, tx) = (tid / 16, tid % 16)
-  // computes rows ty + 16a and columns tx + 16c of the tile (a, c < 4)
+  // 64-row tile of X and S staged in LDS, the product on FP64 matrix cores
   constexpr int TR = 64;
   __shared__ double Ss[kMaxK * kMaxK];
   __shared__ double Xs[TR * kMaxK];
@@ -485,39 +498,20 @@ right_mult_kernel(int64_t d, int k, const double* __restrict__ X, const double* 
   for (int e = threadIdx.x; e < k * k; e += kBlock) Ss[e] = Sb[e];
   for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = Xb[e];
   __syncthreads();
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double acc[4][4];
+  double res[KC][4];
+  tile_times_s<KC>(Xs, Ss, rows, k, upper != 0, res);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int bj = 0; bj < KC; ++bj)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-  for (int l = 0; l < k; ++l) {
-    double xv[4], sv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) xv[a] = (ty + 16 * a < rows) ? Xs[(ty + 16 * a) * k + l] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = tx + 16 * c;
-      sv[c] = (j < k && (!upper || l <= j)) ? Ss[l * k + j] : 0.0;
+    for (int t = 0; t < 4; ++t) {
+      const int r = 16 * w + 4 * t + (lane >> 4), j = 16 * bj + (lane & 15);
+      if (r < rows && j < k) {
+        const int64_t o = (int64_t)b * d * k + (r0 + r) * k + j;
+        if (Q != nullptr) Q[o] = res[bj][t];
+        if (zw != nullptr) zw[o] = (TW)res[bj][t];
+      }
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a], sv[c], acc[a][c]);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int r = ty + 16 * a;
-    if (r >= rows) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = tx + 16 * c;
-      if (j >= k) continue;
-      const int64_t o = (int64_t)b * d * k + (r0 + r) * k + j;
-      if (Q != nullptr) Q[o] = acc[a][c];
-      if (zw != nullptr) zw[o] = (TW)acc[a][c];
-    }
-  }
 }
 
 template <typename TW>
@@ -884,12 +878,16 @@ hipError_t launch_right_mult(int batch, int64_t d, int k, const double* X, const
                              int64_t s_stride, bool upper, double* Q, void* zw, size_t zw_bytes,
                              hipStream_t s) {
   dim3 grid(nblk(d, 64), batch);
-  if (zw == nullptr || zw_bytes == 8)
-    right_mult_kernel<double><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, upper ? 1 : 0, Q,
-                                                       (double*)zw);
-  else
-    right_mult_kernel<float><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, upper ? 1 : 0, Q,
-                                                      (float*)zw);
+  const int up = upper ? 1 : 0;
+  if (zw == nullptr || zw_bytes == 8) {
+    if (k <= 16) right_mult_kernel<double, 1><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, up, Q, (double*)zw);
+    else if (k <= 32) right_mult_kernel<double, 2><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, up, Q, (double*)zw);
+    else right_mult_kernel<double, 4><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, up, Q, (double*)zw);
+  } else {
+    if (k <= 16) right_mult_kernel<float, 1><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, up, Q, (float*)zw);
+    else if (k <= 32) right_mult_kernel<float, 2><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, up, Q, (float*)zw);
+    else right_mult_kernel<float, 4><<<grid, kBlock, 0, s>>>(d, k, X, S, s_stride, up, Q, (float*)zw);
+  }
   return hipGetLastError();
 }
 

@@ -140,14 +140,15 @@ void build_items(Plan* P, const int64_t* offsets, int64_t cr) {
 
 hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
                                  int64_t z_stride, void* tbuf, void* part,
-                                 const WorkItem* items_dev, hipStream_t s) {
+                                 const WorkItem* items_dev, int nitems, hipStream_t s) {
+  if (nitems < 1) return hipSuccess;
   if (P.path == LocalPath::Mfma32 && mfma32_eligible(P.dtype, P.d, lda, k))
-    return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, s);
+    return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A))
-    return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, s);
+    return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (gemm_eligible(P.dtype, P.d, lda, A))
-    return launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
-  return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, s);
+    return launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
+  return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
 }
 
 hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
@@ -268,7 +269,7 @@ hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
     if ((e = hipEventRecord(ev0, P->stream)) != hipSuccess) return e;
   }
   e = launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, p.tbuf, p.part, p.items,
-                            P->stream);
+                            (int)P->plan.items.size(), P->stream);
   if (e != hipSuccess) return e;
   if (ev1 != nullptr) {
     e = (P->timing_slot >= 0) ? capture_event_node(P->stream, ev1) : hipEventRecord(ev1, P->stream);
@@ -713,11 +714,11 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
     hipError_t e = hipSuccess;
     for (int it = 0; it < 2 && e == hipSuccess; ++it)
       e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
-                                P->stream);
+                                (int)P->plan.items.size(), P->stream);
     if (e == hipSuccess) e = hipEventRecord(e0, P->stream);
     for (int it = 0; it < reps && e == hipSuccess; ++it)
       e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
-                                P->stream);
+                                (int)P->plan.items.size(), P->stream);
     if (e == hipSuccess) e = hipEventRecord(e1, P->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -898,7 +899,7 @@ lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y
   if ((st = join_in(P)) != LP_OK) return st;
   LP_HIP(launch_to_working(P->plan, 1, P->d, k, Z, q.Zw_shared, P->stream));
   LP_HIP(launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
-                               P->stream));
+                               (int)P->plan.items.size(), P->stream));
   LP_HIP(launch_reduce_partials(P->plan, k, q.part, q.slot_off, Y_out, P->stream));
   return join_out(P);
 }

@@ -121,36 +121,42 @@ lp_status report(lp_status s, const std::string& msg);
 // kernel launchers (all enqueue on `s`, return the launch status)
 // ---------------------------------------------------------------------------
 
-// Local multiply Y_i = A_i^T (A_i Z_i) for every work item, partial sums per item.
+// Local multiply Y_i = A_i^T (A_i Z_i) for nitems work items starting at items_dev
+// (all of them: plan.items.size()), partial sums per item.
 //   Zw: working copy of the per-partition inputs, z_stride elements between
 //   partitions (0 = one shared Z).  Writes part[slot] (d x k, acc type).
 hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int k,
                                  const void* Zw, int64_t z_stride, void* tbuf, void* part,
-                                 const WorkItem* items_dev, hipStream_t s);
+                                 const WorkItem* items_dev, int nitems,
+                                 hipStream_t s);
 
 // Fused single-pass matrix-core kernel: FP32 A, k = 16, d in {256, 512, 768, 1024}.
 bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k);
 hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
-                                        const WorkItem* items, hipStream_t s);
+                                        const WorkItem* items, int nitems,
+                                        hipStream_t s);
 
 // Fused single-pass matrix-core kernel: BF16 A, k in {16, 32}, d in {512, 1024,
 // 1536, 2048}, rows 16-byte aligned (BF16 operands, FP32 accumulation).
 bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A);
 hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
-                                        const WorkItem* items, hipStream_t s);
+                                        const WorkItem* items, int nitems,
+                                        hipStream_t s);
 
 // Two-pass form on FP32 matrix cores (t = A Z, then A^T t): FP32 or BF16 A,
 // d % 4 == 0, any k <= 64.
 bool gemm_eligible(lp_dtype dtype, int64_t d, int64_t lda, const void* A);
 hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
-                                      const WorkItem* items, hipStream_t s);
+                                      const WorkItem* items, int nitems,
+                                      hipStream_t s);
 
 hipError_t launch_local_multiply_twopass(const Plan& P, const void* A, int64_t lda, int k,
                                          const void* Zw, int64_t z_stride, void* tbuf, void* part,
-                                         const WorkItem* items, hipStream_t s);
+                                         const WorkItem* items, int nitems,
+                                         hipStream_t s);
 
 // Y_i = sum of the partials of partition i in item order (FP64); slot_off is
 // the device int32[m+1] prefix of partial slots per partition.
