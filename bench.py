@@ -16,8 +16,9 @@ value  = algorithmic bytes of A streamed per step (local iterations * n * d * b)
          / step time.
 roofline.achieved = n * d * b bytes (HBM-bound kernels) or 4 n d k flops
 (the matrix-core-bound two-pass kernel) / average duration of one local
-multiply (HIP events around each launch on the library's stream, inside the
-timed steps); peak = the published 8 TB/s or 157.3 TFLOP/s (FP32 matrix).
+multiply (HIP events around the first local multiply of every round, on the
+library's stream, inside the timed steps: bracketing every launch would add a
+few microseconds of stream time per launch to the timed steps); peak = the published 8 TB/s or 157.3 TFLOP/s (FP32 matrix).
 The library's autotuner picks the local-multiply variant before the timed
 region; the measured read and copy bandwidth of simple streaming kernels is
 reported beside the roofline.
@@ -281,13 +282,13 @@ def main():
     iters_per_step = int(sum(sched))
     log(f"warmup x{args.warmup}")
     for _ in range(args.warmup):
-        lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=True)
+        lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=2)
     torch.cuda.synchronize()
     log(f"timed x{args.steps}")
     ms_local, launches, graph_rounds = 0.0, 0, 0
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=True)
+        r = lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=2)
         ms_local += r["stats"]["ms_local"]
         launches += r["stats"]["local_launches"]
         graph_rounds += r["stats"]["graph_rounds"]

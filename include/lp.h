@@ -145,7 +145,10 @@ typedef struct {
   int32_t time_local;   /* 1: bracket every local-multiply launch with a pair of HIP events
                            on the problem's stream (captured as event nodes when rounds are
                            replayed as graphs) and report their summed duration in
-                           stats->ms_local */
+                           stats->ms_local; 2: the same for the first local-multiply launch
+                           of every round only (each event pair costs a few microseconds of
+                           stream time, so sampling keeps the rounds close to untimed
+                           speed); 0: no events */
 } lp_run_opts;
 
 typedef struct {

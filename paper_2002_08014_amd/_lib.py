@@ -269,8 +269,10 @@ def lp_autotune(P: Problem, k: int, cache_path: Optional[str] = None) -> dict:
 
 def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool = False,
            U_ref: Optional[torch.Tensor] = None, record_signs: bool = False,
-           z0_orthonormal: bool = False, use_graph: bool = True, time_local: bool = False):
-    """Returns dict(Z, ritz, sin_hist, signs, stats); Z is a device d x k float64 tensor."""
+           z0_orthonormal: bool = False, use_graph: bool = True, time_local: int = 0):
+    """Returns dict(Z, ritz, sin_hist, signs, stats); Z is a device d x k float64 tensor.
+    time_local: 0 no events, 1 (or True) every local-multiply launch timed,
+    2 the first launch of every round only."""
     L = load()
     dev = P.A.device
     sched = np.ascontiguousarray(np.asarray(p_sched, dtype=np.int32))
@@ -282,7 +284,7 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
     opts.struct_size = ctypes.sizeof(RunOpts)
     opts.z0_orthonormal = 1 if z0_orthonormal else 0
     opts.use_graph = 1 if use_graph else 0
-    opts.time_local = 1 if time_local else 0
+    opts.time_local = int(time_local)
     hist = None
     if U_ref is not None:
         Ud = _dev_f64(U_ref, dev)

@@ -134,54 +134,63 @@ __device__ inline double rdlane(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+// 1 / sqrt(x) for finite x > 0: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2 (each at least doubles the correct bits; the
+// result is within a few ulp, and sqrt(x) is taken as x / sqrt(x)).
+__device__ inline double rsqrt_pos(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+  }
+  return y;
+}
+
 // Cholesky G = R^T R (upper R, positive diagonal) of the k x k LDS matrix G and
-// R^{-1} into the LDS matrix Ri, by the first wavefront of the block: lane c
-// holds column c in registers and rows are broadcast with readlane, so no block
-// barrier is needed inside.  On breakdown (non-positive or non-finite pivot)
-// *bad is set and Ri is the identity.  Call from all threads; returns after a
-// block barrier with Ri ready.
+// R^{-1} into the LDS matrix Ri (row stride k, zero below the diagonal), by the
+// first wavefront of the block (k <= KM <= 32): lane c holds column c of G in
+// registers and rows are broadcast with readlane.  G is padded to KM x KM with
+// the identity, whose factor and inverse are blockdiag(R, I) and
+// blockdiag(R^{-1}, I), so no step branches on k or on the lane.  On breakdown
+// (non-positive or non-finite pivot) *bad is set and Ri is the identity.  Call
+// from all threads; returns after a block barrier with Ri ready.
 template <int KM>
-__device__ void chol_inv_wave(const double* G, double* Ri, int k, int* bad) {
+__device__ __forceinline__ void chol_inv_wave(const double* G, double* Ri, int k, int* bad) {
+  static_assert(KM <= 32, "register-resident factorization for k <= 32");
   if (threadIdx.x < 64) {
     const int c = threadIdx.x;
-    double g[KM], r[KM];
+    const int cc = c < KM ? c : KM - 1;    // lanes past KM shadow the last column
+    double g[KM], r[KM], rd[KM];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) g[i] = (c < k && i < k) ? G[i * k + c] : 0.0;
+    for (int i = 0; i < KM; ++i) {
+      const double v = G[min(i, k - 1) * k + min(cc, k - 1)];
+      g[i] = (i < k && cc < k) ? v : (i == cc ? 1.0 : 0.0);
+    }
     bool badw = false;
+    // column-oriented elimination: step j makes row j of R (lane c: R[j][c]) and
+    // updates the trailing rows; entries below the diagonal are never read
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        double djj = rdlane(g[j], j);
-        if (!(djj > 0.0) || !isfinite(djj)) {
-          badw = true;
-          djj = 1.0;
-        }
-        const double rjj = sqrt(djj);
-        const double rjc = (c == j) ? rjj : ((c > j && c < k) ? g[j] / rjj : 0.0);
-        r[j] = rjc;
+      double djj = rdlane(g[j], j);
+      const bool ok = djj > 0.0 && isfinite(djj);
+      badw = badw || !ok;
+      djj = ok ? djj : 1.0;
+      const double inv = rsqrt_pos(djj);
+      const double rjj = djj * inv;
+      rd[j] = inv;
+      const double rjc = (c == j) ? rjj : (c > j ? g[j] * inv : 0.0);
+      r[j] = rjc;
 #pragma unroll
-        for (int i = j + 1; i < KM; ++i) {
-          if (i < k) {
-            const double rji = rdlane(rjc, i);
-            if (c >= i) g[i] -= rji * rjc;
-          }
-        }
-      } else {
-        r[j] = 0.0;
-      }
+      for (int i = j + 1; i < KM; ++i) g[i] = fma(-rdlane(rjc, i), rjc, g[i]);
     }
-    // back substitution R x = e_c; x overwrites g
+    // back substitution R x = e_c (R[i][l] is lane l's r[i]); x overwrites g
 #pragma unroll
     for (int i = KM - 1; i >= 0; --i) {
-      if (i < k) {
-        double sacc = (i == c) ? 1.0 : 0.0;
+      double acc = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-        for (int l = i + 1; l < KM; ++l)
-          if (l < k) sacc -= rdlane(r[i], l) * g[l];
-        g[i] = sacc / rdlane(r[i], i);
-      } else {
-        g[i] = 0.0;
-      }
+      for (int l = i + 1; l < KM; ++l) acc = fma(-rdlane(r[i], l), g[l], acc);
+      g[i] = acc * rd[i];
     }
     if (c < k) {
 #pragma unroll
@@ -193,7 +202,86 @@ __device__ void chol_inv_wave(const double* G, double* Ri, int k, int* bad) {
   __syncthreads();
 }
 
-
+// The same for any k <= 64 by the whole block (kBlock threads) in LDS: G is
+// overwritten.  Right-looking elimination on the upper triangle with one block
+// barrier per step (the pivot row is read, only rows below it are written):
+// after it row j holds the pivot d_j and the unscaled row, and
+// R[j][c] = G[j][c] / sqrt(d_j).  The inverse solves R X = I the same way from
+// the last row up: X[i][c] = B[i][c] / R[i][i], and every row r < i subtracts
+// R[r][i] X[i][c].  *bad and the identity on breakdown as above.
+__device__ __forceinline__ void chol_inv_block(double* G, double* Ri, int k, int* bad) {
+  __shared__ double rs[kMaxK];   // 1 / sqrt(d_j)
+  __shared__ int badl;
+  const int t = threadIdx.x;
+  const int c = t & 63, r0 = t >> 6;
+  constexpr int kRowStep = kBlock / 64;
+  if (t == 0) badl = 0;
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();   // row j is final
+    double djj = G[j * k + j];
+    if (!(djj > 0.0) || !isfinite(djj)) {
+      djj = 1.0;
+      if (t == 0) badl = 1;
+    }
+    const double inv = 1.0 / djj;
+    if (c > j && c < k) {
+      // rows i = j + 1 + r0 + 4q <= c of column c: all loads first, then the updates
+      const double gjc = G[j * k + c] * inv;
+      double a[kMaxK / kRowStep], v[kMaxK / kRowStep];
+#pragma unroll
+      for (int q = 0; q < kMaxK / kRowStep; ++q) {
+        const int i = min(j + 1 + r0 + kRowStep * q, c);
+        a[q] = G[j * k + i];
+        v[q] = G[i * k + c];
+      }
+#pragma unroll
+      for (int q = 0; q < kMaxK / kRowStep; ++q) {
+        const int i = j + 1 + r0 + kRowStep * q;
+        if (i <= c) G[i * k + c] = fma(-a[q], gjc, v[q]);
+      }
+    }
+  }
+  __syncthreads();
+  if (t < k) {
+    double djj = G[t * k + t];
+    if (!(djj > 0.0) || !isfinite(djj)) djj = 1.0;
+    rs[t] = 1.0 / sqrt(djj);
+  }
+  __syncthreads();
+  // R into G (upper triangle), B = I into Ri
+  for (int e = t; e < k * k; e += kBlock) {
+    const int i = e / k, cc = e - (e / k) * k;
+    const double v = G[e];
+    G[e] = (cc > i) ? v * rs[i] : (cc == i ? 1.0 / rs[i] : 0.0);
+    Ri[e] = (cc == i) ? 1.0 : 0.0;
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    __syncthreads();   // row i of B is final
+    if (c >= i && c < k) {
+      const double xic = Ri[i * k + c] * rs[i];   // 1 / R[i][i] = rs[i]
+      double a[kMaxK / kRowStep], v[kMaxK / kRowStep];
+#pragma unroll
+      for (int q = 0; q < kMaxK / kRowStep; ++q) {
+        const int r = min(r0 + kRowStep * q, i);
+        a[q] = G[r * k + i];
+        v[q] = Ri[r * k + c];
+      }
+#pragma unroll
+      for (int q = 0; q < kMaxK / kRowStep; ++q) {
+        const int r = r0 + kRowStep * q;
+        if (r < i) Ri[r * k + c] = fma(-a[q], xic, v[q]);
+      }
+    }
+  }
+  __syncthreads();
+  const bool fail = badl != 0;
+  for (int e = t; e < k * k; e += kBlock) {
+    const int i = e / k, cc = e - (e / k) * k;
+    Ri[e] = fail ? (cc == i ? 1.0 : 0.0) : Ri[e] * rs[i];
+  }
+  if (t == 0 && fail) *bad = 1;
+  __syncthreads();
+}
 
 // grid (nch, m): Y_i rows of chunk c = sum of the partition's partial slots, and their Gram.
 template <typename TC, int KM>
@@ -250,7 +338,10 @@ chol_inv_wave_kernel(int nch, int k, const double* __restrict__ gin, double* __r
   if (threadIdx.x == 0) bad = 0;
   sum_partials(gin, b, nch, k, G);
   __syncthreads();
-  chol_inv_wave<KM>(G, Ri, k, &bad);
+  if constexpr (KM <= 32)
+    chol_inv_wave<KM>(G, Ri, k, &bad);
+  else
+    chol_inv_block(G, Ri, k, &bad);
   for (int e = threadIdx.x; e < k * k; e += kBlock) rinv[(int64_t)b * k * k + e] = Ri[e];
   if (threadIdx.x == 0 && bad && flags != nullptr) flags[b] = 1;
 }
@@ -288,23 +379,39 @@ __device__ inline void tile_times_s(const double* Xs, const double* S, int rows,
 }
 
 // grid (ceil(d / 64), batch): Q = X R^{-1} for the 64-row chunk c of matrix b
-// (R^{-1} upper triangular, from rinv), the optional working copy, and the
-// optional Gram partial of the chunk's rows of Q (partial index b * gridDim.x + c).
-// X and R^{-1} staged in LDS; thread (ty, tx) computes rows ty + 16a and
-// columns tx + 16c of the chunk.
-template <typename TW, int KC>
+// (R^{-1} upper triangular), the optional working copy, and the optional Gram
+// partial of the chunk's rows of Q (partial index b * gridDim.x + c).  With
+// FACTOR (k <= 16) every workgroup sums the nch_in Gram partials in `rin` and
+// factors and inverts them itself (a few microseconds of one wavefront, cheaper
+// than a separate launch at this k; breakdown sets flags[b] and takes R = I);
+// otherwise `rin` holds R^{-1} of every matrix.  The chunk of X is loaded into
+// LDS before the factorization so that the loads overlap it.
+template <typename TW, int KC, bool FACTOR>
 __global__ void __launch_bounds__(kBlock)
-apply_gram_kernel(int64_t d, int k, const double* __restrict__ X, const double* __restrict__ rinv,
-                  double* __restrict__ Q, TW* __restrict__ zw, double* __restrict__ gout) {
-  __shared__ double Ri[kMaxK * kMaxK];
-  __shared__ double Xs[kGramRows * kMaxK];
+apply_gram_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
+                  const double* __restrict__ rin, double* __restrict__ Q, TW* __restrict__ zw,
+                  double* __restrict__ gout, int32_t* __restrict__ flags) {
+  constexpr int KM = 16 * KC;
+  __shared__ double Ri[KM * KM];
+  __shared__ double Xs[kGramRows * KM];
   const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
   const int64_t r0 = (int64_t)c * kGramRows;
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const int64_t base = (int64_t)b * d * k + r0 * k;
-  for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rinv[(int64_t)b * k * k + e];
   for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = X[base + e];
-  __syncthreads();
+  if constexpr (FACTOR) {
+    static_assert(KC == 1, "in-kernel factorization only for k <= 16");
+    __shared__ double G[KM * KM];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    sum_partials(rin, b, nch_in, k, G);
+    __syncthreads();
+    chol_inv_wave<KM>(G, Ri, k, &bad);
+    if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
+  } else {
+    for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rin[(int64_t)b * k * k + e];
+    __syncthreads();
+  }
   double res[KC][4];
   tile_times_s<KC>(Xs, Ri, rows, k, true, res);
   __syncthreads();   // every wave has read Xs; it now holds the chunk of Q
@@ -327,108 +434,6 @@ apply_gram_kernel(int64_t d, int k, const double* __restrict__ X, const double* 
   }
 }
 
-
-// Cholesky G = R^T R (upper R, positive diagonal) of the k x k LDS matrix G by
-// the first wavefront (lane c holds column c; rows broadcast with readlane),
-// written to the LDS matrix R, with 1/R_jj in rdi.  On breakdown *bad is set
-// and R is the identity.  Call from all threads; ends with a block barrier.
-template <int KM>
-__device__ void chol_wave(const double* G, double* R, double* rdi, int k, int* bad) {
-  if (threadIdx.x < 64) {
-    const int c = threadIdx.x;
-    double g[KM];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) g[i] = (c < k && i < k) ? G[i * k + c] : 0.0;
-    bool badw = false;
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        double djj = rdlane(g[j], j);
-        if (!(djj > 0.0) || !isfinite(djj)) {
-          badw = true;
-          djj = 1.0;
-        }
-        const double rjj = sqrt(djj);
-        const double inv = 1.0 / rjj;
-        const double rjc = (c == j) ? rjj : ((c > j && c < k) ? g[j] * inv : 0.0);
-        if (c < k) R[j * k + c] = rjc;
-        if (c == j) rdi[j] = inv;
-#pragma unroll
-        for (int i = j + 1; i < KM; ++i) {
-          if (i < k) {
-            const double rji = rdlane(rjc, i);
-            if (c >= i) g[i] -= rji * rjc;
-          }
-        }
-      }
-    }
-    if (badw) {
-      for (int e = c; e < k * k; e += 64) R[e] = (e / k == e % k) ? 1.0 : 0.0;
-      if (c < k) rdi[c] = 1.0;
-      if (c == 0) *bad = 1;
-    }
-  }
-  __syncthreads();
-}
-
-// Rows per CholeskyQR chunk so that the chunk's rows fit a 32 KB LDS block.
-template <int KM>
-struct ChunkRows {
-  static constexpr int value = (32768 / 8) / KM;  // 256 for k <= 16, 128 for 32, 64 for 64
-};
-
-// grid (ceil(d / RC), batch): one CholeskyQR pass for a row chunk of matrix b
-// (small k): sum the nch_in Gram partials and factor them in every workgroup
-// (one wavefront; cheaper than a separate launch at this size), forward-
-// substitute Q_row = X_row R^{-1} (one thread per row), and optionally write
-// the working copy and the Gram partial of the chunk's rows (chunk = RC rows,
-// partial index b * gridDim.x + c).
-template <typename TW, int KM>
-__global__ void __launch_bounds__(kBlock)
-chol_solve_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
-                  const double* __restrict__ gin, double* __restrict__ Q, TW* __restrict__ zw,
-                  double* __restrict__ gout, int32_t* __restrict__ flags) {
-  constexpr int RC = ChunkRows<KM>::value;
-  __shared__ double G[KM * KM];
-  __shared__ double R[KM * KM];
-  __shared__ double rdi[KM];
-  __shared__ double qs[RC * KM];
-  __shared__ int bad;
-  const int b = blockIdx.y, c = blockIdx.x, nch_out = gridDim.x;
-  if (threadIdx.x == 0) bad = 0;
-  sum_partials(gin, b, nch_in, k, G);
-  __syncthreads();
-  chol_wave<KM>(G, R, rdi, k, &bad);
-  if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
-  const int64_t r0 = (int64_t)c * RC;
-  const int rows = (int)min<int64_t>(RC, d - r0);
-  for (int rr = threadIdx.x; rr < rows; rr += kBlock) {
-    const double* xr = X + (int64_t)b * d * k + (r0 + rr) * k;
-    double q[KM];
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        double v = xr[j];
-#pragma unroll
-        for (int l = 0; l < j; ++l) v = fma(-q[l], R[l * k + j], v);
-        q[j] = v * rdi[j];
-      }
-    }
-    double* qo = Q + (int64_t)b * d * k + (r0 + rr) * k;
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        qo[j] = q[j];
-        if (zw != nullptr) zw[(int64_t)b * d * k + (r0 + rr) * k + j] = (TW)q[j];
-        qs[rr * k + j] = q[j];
-      }
-    }
-  }
-  if (gout != nullptr) {
-    __syncthreads();
-    gram_tile<kc_of(KM)>(qs, qs, rows, k, gout + ((int64_t)b * nch_out + c) * k * k);
-  }
-}
 
 // grid (nch, batch): partial column dots of chunk c: part[(b*nch + c)*k + j].
 __global__ void __launch_bounds__(kBlock)
@@ -987,9 +992,9 @@ template <typename TW, int KM>
 static hipError_t chol_solve_km(int batch, int64_t d, int k, int nch_in, const double* X,
                                 const double* gin, double* rfac, double* Q, TW* zw, double* gout,
                                 int32_t* flags, hipStream_t s) {
+  const dim3 grid(nblk(d, kGramRows), batch);
   if constexpr (KM <= 16) {
-    dim3 grid(nblk(d, ChunkRows<KM>::value), batch);
-    chol_solve_kernel<TW, KM><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
+    apply_gram_kernel<TW, 1, true><<<grid, kBlock, 0, s>>>(d, k, nch_in, X, gin, Q, zw, gout, flags);
   } else {
     // larger k: factor and invert once per matrix, then multiply the 64-row chunks
     // the Gram partials are summed by a wide launch first (one sum per entry,
@@ -997,8 +1002,8 @@ static hipError_t chol_solve_km(int batch, int64_t d, int k, int nch_in, const d
     double* gsum = rfac + (int64_t)batch * k * k;
     sum_gram_kernel<<<dim3(nblk((int64_t)k * k, kBlock), batch), kBlock, 0, s>>>(nch_in, k * k, gin, gsum);
     chol_inv_wave_kernel<KM><<<batch, kBlock, 0, s>>>(1, k, gsum, rfac, flags);
-    dim3 g2(nblk(d, kGramRows), batch);
-    apply_gram_kernel<TW, kc_of(KM)><<<g2, kBlock, 0, s>>>(d, k, X, rfac, Q, zw, gout);
+    apply_gram_kernel<TW, kc_of(KM), false><<<grid, kBlock, 0, s>>>(d, k, 0, X, rfac, Q, zw, gout,
+                                                                     nullptr);
   }
   return hipGetLastError();
 }
@@ -1012,9 +1017,7 @@ static hipError_t chol_solve_t(int batch, int64_t d, int k, int nch_in, const do
   return chol_solve_km<TW, kMaxK>(batch, d, k, nch_in, X, gin, rfac, Q, zw, gout, flags, s);
 }
 
-int chol_solve_chunks(int64_t d, int k) {
-  return k <= 16 ? nblk(d, ChunkRows<16>::value) : nblk(d, kGramRows);
-}
+int chol_solve_chunks(int64_t d, int /*k*/) { return nblk(d, kGramRows); }
 
 hipError_t launch_chol_solve(int batch, int64_t d, int k, int nch_in, const double* X,
                              const double* gram_in, double* rfac, double* Q, void* zw,

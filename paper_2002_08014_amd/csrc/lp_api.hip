@@ -249,19 +249,20 @@ hipError_t capture_event_node(hipStream_t s, hipEvent_t ev) {
   return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
 }
 
-// One local iteration on every partition: Yi = A_i^T (A_i Z_i).  When timing,
-// the local-multiply launch is bracketed by a pair of events: external event
-// nodes of the timed graph instance being captured, or plain event records.
+// One local iteration on every partition: Yi = A_i^T (A_i Z_i).  When this
+// launch is timed, it is bracketed by a pair of events: external event nodes of
+// the timed graph instance being captured, or plain event records.
 hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
   Ptrs p = ptrs(P);
   hipError_t e;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (P->timing && P->timing_slot >= 0) {
+  const bool timed = P->timing_now;
+  if (timed && P->timing_slot >= 0) {
     const int pair = P->timing_slot * kPairsPerSlot + P->timing_pair++;
     ev0 = P->ev_pool[2 * pair];
     ev1 = P->ev_pool[2 * pair + 1];
     if ((e = capture_event_node(P->stream, ev0)) != hipSuccess) return e;
-  } else if (P->timing) {
+  } else if (timed) {
     if (P->ev_used == kEvPairs && (e = drain_timing(P)) != hipSuccess) return e;
     ev0 = P->ev_pool[2 * P->ev_used];
     ev1 = P->ev_pool[2 * P->ev_used + 1];
@@ -308,7 +309,10 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
           return e;
       }
     }
-    if ((e = local_iter(P, k, zsrc, zstride)) != hipSuccess) return e;
+    P->timing_now = P->timing && (l == 1 || !P->timing_first_only);
+    e = local_iter(P, k, zsrc, zstride);
+    P->timing_now = false;
+    if (e != hipSuccess) return e;
     if (l < p) {
       if ((e = cholqr2_from_gram(P->plan, P->ws, m, d, k, q.Yi, q.Zi, q.Zw, q.flags, s)) !=
           hipSuccess)
@@ -332,7 +336,7 @@ lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool us
     LP_HIP(enqueue_round(P, k, p, mode, hist));
     return LP_OK;
   }
-  GraphKey key{k, p, (int)mode, hist ? 1 : 0, slot};
+  GraphKey key{k, p, (int)mode, hist ? 1 : 0, slot, slot >= 0 && P->timing_first_only ? 1 : 0};
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -777,7 +781,9 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     if (n < offsetof(lp_run_opts, use_graph) + sizeof(int32_t)) o.use_graph = 1;
   }
   const bool hist = o.U_ref != nullptr && o.sin_hist != nullptr;
+  if (o.time_local < 0 || o.time_local > 2) return fail(LP_EINVAL, "time_local must be 0, 1 or 2");
   const bool timing = o.time_local != 0;
+  P->timing_first_only = o.time_local == 2;
   const bool graph = o.use_graph != 0;
   if (timing && P->ev_pool.empty()) {
     P->ev_pool.assign(2 * kEvPairs, nullptr);
@@ -822,7 +828,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
         LP_HIP(harvest_slots(P, pending));
         st = run_round(P, k, p, mode, hist, false, -1);
       } else {
-        pending.emplace_back(slot, p);
+        pending.emplace_back(slot, P->timing_first_only ? 1 : p);
         graph_rounds++;
       }
     } else {

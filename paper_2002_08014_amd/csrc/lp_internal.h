@@ -63,12 +63,14 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
 
 struct GraphKey {
   int32_t k, p, mode, hist, slot;  // slot >= 0: timed instance with its own event pairs
+  int32_t first_only;              // timed instance brackets only the round's first step
   bool operator<(const GraphKey& o) const {
     if (k != o.k) return k < o.k;
     if (p != o.p) return p < o.p;
     if (mode != o.mode) return mode < o.mode;
     if (hist != o.hist) return hist < o.hist;
-    return slot < o.slot;
+    if (slot != o.slot) return slot < o.slot;
+    return first_only < o.first_only;
   }
 };
 
@@ -95,6 +97,8 @@ struct lp_problem {
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
   bool timing = false;
+  bool timing_first_only = false;  // time only the first local step of every round
+  bool timing_now = false;         // the next local-multiply launch is bracketed
   int timing_slot = -1;   // >= 0 while capturing a timed graph instance
   int timing_pair = 0;
   bool timed_graphs_ok = true;
@@ -228,11 +232,11 @@ hipError_t launch_aggregate_gram(int m, int64_t d, int k, const double* Yi, doub
 
 
 
-// One CholeskyQR pass: sum the nch_in Gram partials and factor them (k <= 16:
-// in every row-chunk workgroup, one launch; larger k: once per matrix into
-// rfac = batch x (k*k + k) doubles, then the row chunks), forward-substitute the
-// rows, optionally write the working copy and the Gram partials of Q
-// (chol_solve_chunks(d, k) of them).
+// One CholeskyQR pass: sum the nch_in Gram partials, factor them and invert the
+// factor (k <= 16: in every 64-row-chunk workgroup, one launch; larger k: once
+// per matrix into rfac = batch x 2 k^2 doubles, then the row chunks), multiply
+// the rows by R^{-1} on FP64 matrix cores, optionally write the working copy
+// and the Gram partials of Q (chol_solve_chunks(d, k) of them).
 hipError_t launch_chol_solve(int batch, int64_t d, int k, int nch_in, const double* X,
                              const double* gram_in, double* rfac, double* Q, void* zw,
                              size_t zw_bytes, double* gram_out, int32_t* flags, hipStream_t s);

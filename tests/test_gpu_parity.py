@@ -125,10 +125,13 @@ def test_local_multiply(lib, dtype, k):
         assert np.all(np.abs(Y[i] - ref) <= gamma * bound + 1e-300), (i, np.abs(Y[i] - ref).max())
 
 
-def test_orth_batched(lib):
-    _flush("orth")
-    rng = np.random.default_rng(3)
-    d, k, b = 333, 9, 3
+@pytest.mark.parametrize("k", [9, 16, 32, 40, 64])
+def test_orth_batched(lib, k):
+    """CholeskyQR2 of a batch: k <= 16 factors in every row-chunk workgroup,
+    17..32 in one wavefront per matrix, larger k block-wide per matrix."""
+    _flush(f"orth k={k}")
+    rng = np.random.default_rng(3 + k)
+    d, b = 333, 3
     w = synth.make_small(400, d, 4, 4, seed=1)
     P = _problem(lib, to_device(w), w.offsets, k)
     Y = rng.standard_normal((b, d, k)) @ np.diag(np.logspace(0, -4, k))
@@ -140,15 +143,18 @@ def test_orth_batched(lib):
         assert np.abs(Q[i].T @ Q[i] - np.eye(k)).max() < 1e-14
 
 
-def test_orth_breakdown_flag(lib):
-    """A rank-deficient iterate is reported (host-forced: a zero column)."""
-    _flush("orth breakdown")
+@pytest.mark.parametrize("k", [4, 24, 40])
+def test_orth_breakdown_flag(lib, k):
+    """A rank-deficient iterate is reported (host-forced: a zero column), on
+    each of the three factorization paths; the other matrix of the batch is not."""
+    _flush(f"orth breakdown k={k}")
     w = synth.make_small(200, 50, 4, 4, seed=1)
-    P = _problem(lib, to_device(w), w.offsets, 4)
-    Y = np.random.default_rng(0).standard_normal((1, 50, 4))
+    P = _problem(lib, to_device(w), w.offsets, k)
+    Y = np.random.default_rng(0).standard_normal((2, 50, k))
     Y[0, :, 2] = 0.0
-    _, flags = lib.lp_orth(P, torch.as_tensor(Y, device="cuda:0"))
-    assert int(flags[0]) == 1
+    Q, flags = lib.lp_orth(P, torch.as_tensor(Y, device="cuda:0"))
+    assert int(flags[0]) == 1 and int(flags[1]) == 0
+    assert np.abs(host(Q)[1] - oracle.orth(Y[1])).max() < 1e-12
 
 
 def test_align(lib):
@@ -286,3 +292,12 @@ def test_timed_graph_rounds(lib, fp64_small):
         assert st["local_launches"] == sum(sched) and st["ms_local"] > 0
     assert r1["stats"]["graph_rounds"] == len(sched)
     assert r2["stats"]["graph_rounds"] == 0
+    # sampled timing: only the first local multiply of every round, same result
+    r3 = lib.lp_run(P, w.k, sched, "sign", w.Y0, time_local=2)
+    r4 = lib.lp_run(P, w.k, sched, "sign", w.Y0, time_local=2, use_graph=False)
+    for r in (r3, r4):
+        assert torch.equal(r0["Z"], r["Z"])
+        assert r["stats"]["local_launches"] == len(sched) and r["stats"]["ms_local"] > 0
+    assert r3["stats"]["graph_rounds"] == len(sched)
+    with pytest.raises(lib.LPError):
+        lib.lp_run(P, w.k, sched, "sign", w.Y0, time_local=3)
