@@ -18,7 +18,9 @@ roofline.achieved = n * d * b bytes (HBM-bound kernels) or 4 n d k flops
 (the matrix-core-bound two-pass kernel) / average duration of one local
 multiply (HIP events around the first local multiply of every round, on the
 library's stream, inside the timed steps: bracketing every launch would add a
-few microseconds of stream time per launch to the timed steps); peak = the published 8 TB/s or 157.3 TFLOP/s (FP32 matrix).
+few microseconds of stream time per launch to the timed steps; when the rounds
+run split in two halves on two streams, one pair brackets both halves' launches,
+which run back to back); peak = the published 8 TB/s or 157.3 TFLOP/s (FP32 matrix).
 The library's autotuner picks the local-multiply variant before the timed
 region; the measured read and copy bandwidth of simple streaming kernels is
 reported beside the roofline.
@@ -285,13 +287,14 @@ def main():
         lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=2)
     torch.cuda.synchronize()
     log(f"timed x{args.steps}")
-    ms_local, launches, graph_rounds = 0.0, 0, 0
+    ms_local, launches, graph_rounds, split = 0.0, 0, 0, False
     t0 = time.perf_counter()
     for i in range(args.steps):
         r = lp.lp_run(P, k, sched, w.mode, w.Y0, time_local=2)
         ms_local += r["stats"]["ms_local"]
         launches += r["stats"]["local_launches"]
         graph_rounds += r["stats"]["graph_rounds"]
+        split = bool(r["stats"]["split_rounds"])
         log(f"step {i} done")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -331,7 +334,7 @@ def main():
                    "n": n, "d": d, "k": k, "m": w.m, "p_sched": sched if len(ps) > 1 else ps[0],
                    "rounds": len(sched), "local_iters_per_step": iters_per_step,
                    "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
-                   "tuning": tuning, "graph_rounds": graph_rounds,
+                   "tuning": tuning, "graph_rounds": graph_rounds, "split_rounds": split,
                    "rounds_total": args.steps * len(sched)},
         "roofline": roof,
     }

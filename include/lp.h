@@ -149,19 +149,29 @@ typedef struct {
                            of every round only (each event pair costs a few microseconds of
                            stream time, so sampling keeps the rounds close to untimed
                            speed); 0: no events */
+  int32_t split_rounds;  /* with m >= 2, run the partitions in two halves on two streams,
+                            each half's orthonormalisations and alignment overlapping the
+                            other half's local multiplies (bitwise the same results):
+                            1 always, 2 never, 0 (default) when rank k's local multiply
+                            runs on the two-pass kernels (many workgroups per work item,
+                            so each half still fills the GPU; the fused kernels run one
+                            workgroup per item, and half the items leave half the chip
+                            idle) */
 } lp_run_opts;
 
 typedef struct {
   int32_t rounds;          /* communication rounds completed */
   int32_t local_iters;     /* local power iterations per node completed */
   int32_t breakdowns;      /* Cholesky breakdowns detected (0 on success) */
-  int32_t near_singular;   /* OPT alignments whose Z_i^T Z_b had sigma_min < 1e-12 sigma_max */
+  int32_t near_singular;   /* OPT alignments whose Z_i^T Z_b was singular or too close to
+                              singular for the polar iteration to converge (O not unique) */
   double ms_total;         /* duration of the rounds on the stream (HIP events) */
   double bytes_A;          /* algorithmic bytes of A streamed: local_iters * n * d * elem */
   double ms_local;         /* with opts->time_local: summed duration of the local-multiply
                               launches (HIP events), else 0 */
   int32_t local_launches;  /* local-multiply launches timed into ms_local */
   int32_t graph_rounds;    /* rounds replayed from captured hipGraphs */
+  int32_t split_rounds;    /* 1 when the rounds ran in two halves on two streams */
 } lp_run_stats;
 
 /* Run LocalPower (Algorithm 1) for T communication rounds.

@@ -50,7 +50,8 @@ class RunOpts(ctypes.Structure):
                 ("signs_out", ctypes.POINTER(ctypes.c_int8)),
                 ("z0_orthonormal", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32),
-                ("time_local", ctypes.c_int32)]
+                ("time_local", ctypes.c_int32),
+                ("split_rounds", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -62,7 +63,8 @@ class RunStats(ctypes.Structure):
                 ("bytes_A", ctypes.c_double),
                 ("ms_local", ctypes.c_double),
                 ("local_launches", ctypes.c_int32),
-                ("graph_rounds", ctypes.c_int32)]
+                ("graph_rounds", ctypes.c_int32),
+                ("split_rounds", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -269,10 +271,12 @@ def lp_autotune(P: Problem, k: int, cache_path: Optional[str] = None) -> dict:
 
 def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool = False,
            U_ref: Optional[torch.Tensor] = None, record_signs: bool = False,
-           z0_orthonormal: bool = False, use_graph: bool = True, time_local: int = 0):
+           z0_orthonormal: bool = False, use_graph: bool = True, time_local: int = 0,
+           split_rounds: Optional[bool] = None):
     """Returns dict(Z, ritz, sin_hist, signs, stats); Z is a device d x k float64 tensor.
-    time_local: 0 no events, 1 (or True) every local-multiply launch timed,
-    2 the first launch of every round only."""
+    time_local: 0 no events, 1 (or True) every local multiply timed, 2 the first
+    one of every round only.  split_rounds: partitions in two halves on two streams
+    (None: the library decides, True: always, False: never)."""
     L = load()
     dev = P.A.device
     sched = np.ascontiguousarray(np.asarray(p_sched, dtype=np.int32))
@@ -285,6 +289,7 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
     opts.z0_orthonormal = 1 if z0_orthonormal else 0
     opts.use_graph = 1 if use_graph else 0
     opts.time_local = int(time_local)
+    opts.split_rounds = 0 if split_rounds is None else (1 if split_rounds else 2)
     hist = None
     if U_ref is not None:
         Ud = _dev_f64(U_ref, dev)

@@ -283,14 +283,15 @@ __device__ __forceinline__ void chol_inv_block(double* G, double* Ri, int k, int
   __syncthreads();
 }
 
-// grid (nch, m): Y_i rows of chunk c = sum of the partition's partial slots, and their Gram.
+// grid (nch, nb): Y_i rows of chunk c = sum of the partition's partial slots, and
+// their Gram, for partition i = b0 + blockIdx.y.
 template <typename TC, int KM>
 __global__ void __launch_bounds__(kBlock)
-reduce_gram_kernel(int64_t d, int k, const TC* __restrict__ part,
+reduce_gram_kernel(int64_t d, int k, int b0, const TC* __restrict__ part,
                    const int32_t* __restrict__ slot_off, double* __restrict__ Yi,
                    double* __restrict__ gram) {
   __shared__ double ys[kGramRows * KM];
-  const int b = blockIdx.y, c = blockIdx.x, nch = gridDim.x;
+  const int b = b0 + (int)blockIdx.y, c = blockIdx.x, nch = gridDim.x;
   const int64_t r0 = (int64_t)c * kGramRows;
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const int64_t dk = d * k;
@@ -647,7 +648,7 @@ __device__ void jacobi_sym_lds(double* S, double* V, int k, double* cs, double* 
 // sqrt(max row sum of |C^T C|) >= sigma_max(C), which converges (quadratically
 // at the end) for every nonsingular C; it stops one iteration after
 // max|X^T X - I| <= 1e-13.  A C that does not converge within the cap (singular
-// or nearly so, where O is not unique) sets flags[b].  grid (batch)
+// or nearly so, where O is not unique) adds one to *flags.  grid (batch)
 // ---------------------------------------------------------------------------
 template <int KC>
 __global__ void __launch_bounds__(kBlock)
@@ -722,7 +723,7 @@ polar_kernel(int nchunks, int k, const double* part, double* O, int32_t* flags) 
       }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && flags != nullptr && (!converged || s2 == 0.0)) flags[b] = 1;
+  if (threadIdx.x == 0 && flags != nullptr && (!converged || s2 == 0.0)) atomicAdd(flags, 1);
   double* Ob = O + (int64_t)b * kk;
   for (int e = threadIdx.x; e < kk; e += kBlock) Ob[e] = X[e];
 }
@@ -957,18 +958,19 @@ hipError_t launch_sin_theta(int64_t d, int k, const double* Z, const double* U, 
 
 
 hipError_t launch_reduce_gram(const Plan& P, int k, const void* part, const int32_t* slot_off,
-                              double* Yi, double* gram, hipStream_t s) {
-  dim3 grid(nblk(P.d, kGramRows), P.m);
+                              double* Yi, double* gram, int b0, int nb, hipStream_t s) {
+  if (nb < 1) return hipSuccess;
+  dim3 grid(nblk(P.d, kGramRows), nb);
   if (P.acc_bytes == 8) {
     const double* pp = (const double*)part;
-    if (k <= 16) reduce_gram_kernel<double, 16><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
-    else if (k <= 32) reduce_gram_kernel<double, 32><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
-    else reduce_gram_kernel<double, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
+    if (k <= 16) reduce_gram_kernel<double, 16><<<grid, kBlock, 0, s>>>(P.d, k, b0, pp, slot_off, Yi, gram);
+    else if (k <= 32) reduce_gram_kernel<double, 32><<<grid, kBlock, 0, s>>>(P.d, k, b0, pp, slot_off, Yi, gram);
+    else reduce_gram_kernel<double, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, b0, pp, slot_off, Yi, gram);
   } else {
     const float* pp = (const float*)part;
-    if (k <= 16) reduce_gram_kernel<float, 16><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
-    else if (k <= 32) reduce_gram_kernel<float, 32><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
-    else reduce_gram_kernel<float, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, pp, slot_off, Yi, gram);
+    if (k <= 16) reduce_gram_kernel<float, 16><<<grid, kBlock, 0, s>>>(P.d, k, b0, pp, slot_off, Yi, gram);
+    else if (k <= 32) reduce_gram_kernel<float, 32><<<grid, kBlock, 0, s>>>(P.d, k, b0, pp, slot_off, Yi, gram);
+    else reduce_gram_kernel<float, kMaxK><<<grid, kBlock, 0, s>>>(P.d, k, b0, pp, slot_off, Yi, gram);
   }
   return hipGetLastError();
 }

@@ -152,13 +152,14 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
 }
 
 hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
-                             double* Q, void* zw, int32_t* flags, hipStream_t s) {
+                             double* Q, void* zw, int32_t* flags, hipStream_t s, int b0) {
   const Layout& L = P.L;
-  double* gram = (double*)(ws + L.gram);
-  double* gram2 = (double*)(ws + L.gram2);
-  double* tmp = (double*)(ws + L.tmp);
-  double* rfac = (double*)(ws + L.rinv);
   const int nch = (int)((d + kGramRows - 1) / kGramRows);
+  const int64_t kk = (int64_t)k * k;
+  double* gram = (double*)(ws + L.gram) + (int64_t)b0 * nch * kk;
+  double* gram2 = (double*)(ws + L.gram2) + (int64_t)b0 * nch * kk;
+  double* tmp = (double*)(ws + L.tmp) + (int64_t)b0 * d * k;
+  double* rfac = (double*)(ws + L.rinv) + (int64_t)b0 * 2 * kk;
   hipError_t e;
   // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}, and the Gram partials of Q1
   if ((e = launch_chol_solve(batch, d, k, nch, Y, gram, rfac, tmp, nullptr, 0, gram2, flags, s)) !=
@@ -276,12 +277,109 @@ hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
     e = (P->timing_slot >= 0) ? capture_event_node(P->stream, ev1) : hipEventRecord(ev1, P->stream);
     if (e != hipSuccess) return e;
   }
-  return launch_reduce_gram(P->plan, k, p.part, p.slot_off, p.Yi, p.gram, P->stream);
+  return launch_reduce_gram(P->plan, k, p.part, p.slot_off, p.Yi, p.gram, 0, P->m, P->stream);
+}
+
+// Bracket the next launch on stream s with the timing pair (ev0 before it) or
+// close the bracket after it (ev1): external event nodes of the timed graph
+// instance being captured, or plain event records.
+hipError_t timing_mark(lp_problem* P, hipStream_t s, hipEvent_t ev) {
+  return (P->timing_slot >= 0) ? capture_event_node(s, ev) : hipEventRecord(ev, s);
+}
+
+// Take the next pair of timing events (graph slot pair or plain pool pair).
+hipError_t timing_pair(lp_problem* P, hipEvent_t* ev0, hipEvent_t* ev1) {
+  if (P->timing_slot >= 0) {
+    const int pair = P->timing_slot * kPairsPerSlot + P->timing_pair++;
+    *ev0 = P->ev_pool[2 * pair];
+    *ev1 = P->ev_pool[2 * pair + 1];
+    return hipSuccess;
+  }
+  if (P->ev_used == kEvPairs) {
+    hipError_t e = drain_timing(P);
+    if (e != hipSuccess) return e;
+  }
+  *ev0 = P->ev_pool[2 * P->ev_used];
+  *ev1 = P->ev_pool[2 * P->ev_used + 1];
+  P->ev_used++;
+  return hipSuccess;
+}
+
+// One communication round with the partitions in two halves on two streams
+// (Algorithm 1; the same operations and the same arithmetic per partition as
+// the one-stream round, only the order across partitions differs).  The local
+// multiplies form one chain: half 0 then half 1 of step l, then half 0 of step
+// l + 1, so each half's reduction, CholeskyQR2 and alignment run while the
+// other half streams A.  Half 0 holds the base partition; half 1 aligns after
+// the base's last local orthonormalisation.  The two halves join before the
+// aggregation.  When the step is timed, one pair of events brackets both
+// halves' local multiplies (back to back in the chain).
+hipError_t enqueue_round_split(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
+  Ptrs q = ptrs(P);
+  const int64_t d = P->d;
+  const int64_t dk = d * k;
+  const int64_t kk = (int64_t)k * k;
+  const int nch = P->plan.n_gram_chunks;
+  const size_t zwb = P->plan.zw_bytes;
+  const hipStream_t st[2] = {P->stream, P->stream2};
+  hipError_t e;
+#define LP_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+  LP_TRY(hipEventRecord(P->ev_fork, st[0]));
+  LP_TRY(hipStreamWaitEvent(st[1], P->ev_fork, 0));
+  const double* Zb = q.Zi + (int64_t)P->base * dk;
+  for (int l = 1; l <= p; ++l) {
+    const void* zsrc = (l == 1) ? q.Zw_shared : q.Zw;
+    const int64_t zstride = (l == 1) ? 0 : dk;
+    const bool timed = P->timing && (l == 1 || !P->timing_first_only);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (timed) LP_TRY(timing_pair(P, &ev0, &ev1));
+    for (int h = 0; h < 2; ++h) {
+      const Half& H = P->half[h];
+      const hipStream_t s = st[h];
+      double* Zi = q.Zi + (int64_t)H.b0 * dk;
+      void* zw = (char*)q.Zw + (size_t)H.b0 * dk * zwb;
+      double* gram = q.gram + (int64_t)H.b0 * nch * kk;
+      if (l == p && p >= 2 && mode != LP_AGG_VANILLA) {
+        if (h == 1) LP_TRY(hipStreamWaitEvent(s, P->ev_base, 0));
+        if (mode == LP_AGG_SIGN) {
+          LP_TRY(launch_diag_dot(H.nb, d, k, Zi, Zb, gram, s));
+          LP_TRY(launch_sign_apply(H.nb, d, k, gram, Zi, zw, zwb, q.sgn + (int64_t)H.b0 * k, s));
+        } else {
+          double* O = q.omat + (int64_t)H.b0 * kk;
+          LP_TRY(launch_cross_gram(H.nb, d, k, Zi, dk, Zb, 0, gram, s));
+          LP_TRY(launch_procrustes(H.nb, nch, k, gram, O, q.flags + P->m + 1, s));
+          LP_TRY(launch_right_mult(H.nb, d, k, Zi, O, kk, false, nullptr, zw, zwb, s));
+        }
+      }
+      // the chain of local multiplies: after the other half's previous one
+      if (l > 1 || h == 1) LP_TRY(hipStreamWaitEvent(s, P->ev_k1[1 - h], 0));
+      if (timed && h == 0) LP_TRY(timing_mark(P, s, ev0));
+      LP_TRY(launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, q.tbuf, q.part,
+                                   q.items + H.it0, H.nit, s));
+      if (timed && h == 1) LP_TRY(timing_mark(P, s, ev1));
+      LP_TRY(hipEventRecord(P->ev_k1[h], s));
+      LP_TRY(launch_reduce_gram(P->plan, k, q.part, q.slot_off, q.Yi, q.gram, H.b0, H.nb, s));
+      if (l < p) {
+        LP_TRY(cholqr2_from_gram(P->plan, P->ws, H.nb, d, k, q.Yi + (int64_t)H.b0 * dk, Zi, zw,
+                                 q.flags + H.b0, s, H.b0));
+        if (h == 0 && l == p - 1) LP_TRY(hipEventRecord(P->ev_base, s));
+      }
+    }
+  }
+  LP_TRY(hipEventRecord(P->ev_join2, st[1]));
+  LP_TRY(hipStreamWaitEvent(st[0], P->ev_join2, 0));
+  const hipStream_t s = st[0];
+  LP_TRY(launch_aggregate_gram(P->m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, q.gram, s));
+  LP_TRY(cholqr2_from_gram(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + P->m, s));
+  if (hist) LP_TRY(launch_sin_theta(d, k, q.Z, q.Uref, nullptr, q.hist, q.ctr, s));
+#undef LP_TRY
+  return hipSuccess;
 }
 
 // Enqueue one communication round with p local steps (only kernel launches, so
 // the sequence can be captured into a graph).
 hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
+  if (P->split_now) return enqueue_round_split(P, k, p, mode, hist);
   Ptrs q = ptrs(P);
   hipStream_t s = P->stream;
   const int m = P->m;
@@ -336,7 +434,8 @@ lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool us
     LP_HIP(enqueue_round(P, k, p, mode, hist));
     return LP_OK;
   }
-  GraphKey key{k, p, (int)mode, hist ? 1 : 0, slot, slot >= 0 && P->timing_first_only ? 1 : 0};
+  GraphKey key{k, p, (int)mode, hist ? 1 : 0, slot, slot >= 0 && P->timing_first_only ? 1 : 0,
+               P->split_now ? 1 : 0};
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -423,6 +522,19 @@ lp_status upload_items(lp_problem* P) {
   LP_HIP(hipMemcpyAsync(p.slot_off, slot_off.data(), (m + 1) * sizeof(int32_t),
                         hipMemcpyHostToDevice, P->stream));
   LP_HIP(hipStreamSynchronize(P->stream));
+  // halves for split rounds: cut where the rows reach half of n (at least one
+  // partition on each side); half 0 is the side that holds the base partition
+  P->can_split = m >= 2;
+  if (P->can_split) {
+    int cut = 1;
+    while (cut < m - 1 && 2 * P->offsets[cut] < P->n) ++cut;
+    int item_cut = 0;
+    while (item_cut < (int)P->plan.items.size() && P->plan.items[item_cut].part < cut) ++item_cut;
+    const Half lo{0, cut, 0, item_cut};
+    const Half hi{cut, m - cut, item_cut, (int)P->plan.items.size() - item_cut};
+    P->half[0] = P->base < cut ? lo : hi;
+    P->half[1] = P->base < cut ? hi : lo;
+  }
   return LP_OK;
 }
 
@@ -461,6 +573,7 @@ lp_status drive_begin(lp_problem* P, int k, const double* Y0, bool orthonormal) 
 
 lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode) {
   if (p < 1) return fail(LP_EINVAL, "p must be >= 1");
+  P->split_now = false;   // served jobs keep to their own stream
   return run_round(P, k, p, mode, false, true, -1);
 }
 
@@ -551,6 +664,9 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
   P->user_stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&P->ev_fork, &P->ev_join2, &P->ev_base, &P->ev_k1[0], &P->ev_k1[1]})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join_out, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreate(&P->ev_t0);
@@ -582,6 +698,12 @@ lp_status lp_destroy(lp_problem* P) {
     (void)hipStreamSynchronize(P->stream);
     (void)hipStreamDestroy(P->stream);
   }
+  if (P->stream2) {
+    (void)hipStreamSynchronize(P->stream2);
+    (void)hipStreamDestroy(P->stream2);
+  }
+  for (hipEvent_t ev : {P->ev_fork, P->ev_join2, P->ev_base, P->ev_k1[0], P->ev_k1[1]})
+    if (ev) (void)hipEventDestroy(ev);
   if (P->ev_join_in) (void)hipEventDestroy(P->ev_join_in);
   if (P->ev_join_out) (void)hipEventDestroy(P->ev_join_out);
   if (P->ev_t0) (void)hipEventDestroy(P->ev_t0);
@@ -782,6 +904,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   }
   const bool hist = o.U_ref != nullptr && o.sin_hist != nullptr;
   if (o.time_local < 0 || o.time_local > 2) return fail(LP_EINVAL, "time_local must be 0, 1 or 2");
+  if (o.split_rounds < 0 || o.split_rounds > 2) return fail(LP_EINVAL, "split_rounds must be 0, 1 or 2");
   const bool timing = o.time_local != 0;
   P->timing_first_only = o.time_local == 2;
   const bool graph = o.use_graph != 0;
@@ -811,6 +934,12 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   LP_HIP(hipEventRecord(P->ev_t0, s));
   int rounds = 0, iters = 0, hist_done = 0, graph_rounds = 0;
   P->timing = timing;
+  {
+    const bool fused = (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, d, P->lda, k)) ||
+                       (P->plan.path == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, d, P->lda, k, P->A));
+    P->split_now = P->can_split && (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
+  }
+  const bool split = P->split_now;
   std::vector<std::pair<int, int>> pending;  // (slot, p) of timed graph rounds not yet harvested
   for (int r = 0; r < T; ++r) {
     const int p = p_sched[r];
@@ -837,6 +966,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     }
     if (st != LP_OK) {
       P->timing = false;
+      P->split_now = false;
       return st;
     }
     if ((int)pending.size() == kTimedSlots || (r == T - 1 && !pending.empty()))
@@ -860,6 +990,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
       hist_done = rounds;
     }
   }
+  P->split_now = false;
   LP_HIP(hipEventRecord(P->ev_t1, s));
   if (timing) LP_HIP(drain_timing(P));
   P->timing = false;
@@ -892,6 +1023,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     stats->ms_local = P->ms_local;
     stats->local_launches = P->local_launches;
     stats->graph_rounds = graph_rounds;
+    stats->split_rounds = split ? 1 : 0;
   }
   if (breakdowns) return fail(LP_EBREAKDOWN, "Cholesky breakdown in an orthonormalisation");
   return LP_OK;

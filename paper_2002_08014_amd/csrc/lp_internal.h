@@ -64,14 +64,22 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
 struct GraphKey {
   int32_t k, p, mode, hist, slot;  // slot >= 0: timed instance with its own event pairs
   int32_t first_only;              // timed instance brackets only the round's first step
+  int32_t split;                   // partitions in two halves on two streams
   bool operator<(const GraphKey& o) const {
     if (k != o.k) return k < o.k;
     if (p != o.p) return p < o.p;
     if (mode != o.mode) return mode < o.mode;
     if (hist != o.hist) return hist < o.hist;
     if (slot != o.slot) return slot < o.slot;
-    return first_only < o.first_only;
+    if (first_only != o.first_only) return first_only < o.first_only;
+    return split < o.split;
   }
+};
+
+// One half of the partitions for split rounds: partitions [b0, b0 + nb) and
+// their work items [it0, it0 + nit) (items are in partition order).
+struct Half {
+  int32_t b0, nb, it0, nit;
 };
 
 constexpr int kTimedSlots = 8;      // timed graph instances replayed before one harvest
@@ -104,6 +112,15 @@ struct lp_problem {
   bool timed_graphs_ok = true;
   double ms_local = 0.0;
   int local_launches = 0;
+  // split rounds: half[0] holds the base partition and runs on `stream`, half[1]
+  // on stream2; events order the two streams (fork/join, the chain of local
+  // multiplies, the base iterate for the alignment)
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join2 = nullptr, ev_base = nullptr;
+  hipEvent_t ev_k1[2] = {nullptr, nullptr};
+  bool can_split = false;   // m >= 2
+  bool split_now = false;   // the rounds being enqueued are split
+  lp::Half half[2];
 };
 
 namespace lp {
@@ -192,7 +209,8 @@ hipError_t launch_sign_from_gram(int batch, int nchunks, int k, const double* gr
 
 
 // Procrustes factor O_b = W1 W2^T of C_b = sum of cross-gram partials (the orthogonal
-// polar factor of C_b, by Newton-Schulz iteration in FP64).
+// polar factor of C_b, by Newton-Schulz iteration in FP64); *flags (if not null)
+// counts the C_b too close to singular for the iteration to converge.
 hipError_t launch_procrustes(int batch, int nchunks, int k, const double* gram_part,
                              double* O, int32_t* flags, hipStream_t s);
 
@@ -221,9 +239,10 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 hipError_t sin_slot_address(double** p);
 
 // Y_i = sum of partials (item order, FP64) and the Gram partials of Y_i's row
-// chunks (kGramRows rows) into gram; grid over (row chunks, partitions).
+// chunks (kGramRows rows) into gram, for the partitions [b0, b0 + nb); grid over
+// (row chunks, partitions).
 hipError_t launch_reduce_gram(const Plan& P, int k, const void* part, const int32_t* slot_off,
-                              double* Yi, double* gram, hipStream_t s);
+                              double* Yi, double* gram, int b0, int nb, hipStream_t s);
 
 // Y = scale * sum_i Yi and the Gram partials of Y's row chunks into gram.
 hipError_t launch_aggregate_gram(int m, int64_t d, int k, const double* Yi, double scale, double* Y,
@@ -250,8 +269,11 @@ hipError_t launch_sign_apply(int batch, int64_t d, int k, const double* part, do
                              size_t zw_bytes, int8_t* sgn, hipStream_t s);
 
 // CholeskyQR2 when the Gram partials of Y are already in the plan's gram buffer.
+// b0: index of the first matrix of the batch among the plan's matrices (its
+// partials and scratch are at that offset, so disjoint batches may run
+// concurrently on different streams); Y, Q, zw and flags point at the batch.
 hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
-                             double* Q, void* zw, int32_t* flags, hipStream_t s);
+                             double* Q, void* zw, int32_t* flags, hipStream_t s, int b0 = 0);
 
 // CholeskyQR2: Q_b = orth(Y_b) for a batch of d x k FP64 matrices, using
 // gram/rinv scratch from the plan; also writes the working copy when zw != NULL.

@@ -301,3 +301,49 @@ def test_timed_graph_rounds(lib, fp64_small):
     assert r3["stats"]["graph_rounds"] == len(sched)
     with pytest.raises(lib.LPError):
         lib.lp_run(P, w.k, sched, "sign", w.Y0, time_local=3)
+
+
+# --------------------------------------------------------------------- split rounds
+
+@pytest.mark.parametrize("mode", ["sign", "opt", "vanilla"])
+@pytest.mark.parametrize("dtype,k", [(torch.float64, 8), (torch.float32, 16), (torch.float32, 40)])
+def test_split_rounds_match_one_stream(lib, mode, dtype, k):
+    """Rounds split into two halves on two streams give the same bits as the
+    one-stream rounds (every partition's arithmetic is unchanged; only the order
+    across partitions differs), graph-replayed and plain, and agree with the
+    oracle.  Uneven partitions, so the largest (base) partition can sit in
+    either half; p = 1 rounds included."""
+    _flush(f"split rounds {mode} {dtype} k={k}")
+    sched = [4, 3, 1, 2, 4]
+    w = synth.make_small(6000, 96, k, 7, seed=k + 3, uneven=True, p_sched=sched)
+    A_dev = to_device(w, dtype)
+    P = _problem(lib, A_dev, w.offsets, k)
+    r1 = lib.lp_run(P, k, sched, mode, w.Y0, split_rounds=False, record_signs=True)
+    r2 = lib.lp_run(P, k, sched, mode, w.Y0, split_rounds=True, record_signs=True)
+    r3 = lib.lp_run(P, k, sched, mode, w.Y0, split_rounds=True, use_graph=False,
+                    record_signs=True)
+    r4 = lib.lp_run(P, k, sched, mode, w.Y0, split_rounds=True, time_local=1)
+    r5 = lib.lp_run(P, k, sched, mode, w.Y0)      # the library's choice
+    for r in (r2, r3, r4, r5):
+        assert torch.equal(r1["Z"], r["Z"])
+    assert np.array_equal(r1["signs"], r2["signs"]) and np.array_equal(r1["signs"], r3["signs"])
+    assert r4["stats"]["local_launches"] == sum(sched)
+    assert r1["stats"]["split_rounds"] == 0 and r2["stats"]["split_rounds"] == 1
+    ro = oracle.localpower(upcast(A_dev), w.offsets, k, sched, mode, w.Y0)
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    assert sin_theta_np(host(r2["Z"]), ro["Z"]) < tol
+
+
+def test_split_rounds_base_in_second_half(lib):
+    """The largest partition last: the half that holds it runs first."""
+    _flush("split rounds, base last")
+    n, d, k = 4000, 64, 6
+    offsets = np.array([0, 500, 1000, 1500, 4000], dtype=np.int64)
+    w = synth.make_small(n, d, k, 4, seed=2, p_sched=[3, 3, 3])
+    P = _problem(lib, to_device(w), offsets, k)
+    for mode in ("sign", "opt"):
+        r1 = lib.lp_run(P, k, w.p_sched, mode, w.Y0, split_rounds=False)
+        r2 = lib.lp_run(P, k, w.p_sched, mode, w.Y0, split_rounds=True)
+        assert torch.equal(r1["Z"], r2["Z"])
+        ro = oracle.localpower(w.A.numpy(), offsets, k, w.p_sched, mode, w.Y0)
+        assert sin_theta_np(host(r2["Z"]), ro["Z"]) < 1e-10
