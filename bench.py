@@ -111,6 +111,60 @@ def cpu_baseline(w, budget_s=12.0):
                       f"stored width ({b} B) like the GPU figure"}
 
 
+def precision_report(lp, synth, w, P, tuning, sched):
+    """The precision form's operand modes and storage forms, each a full run of
+    the workload's schedule with the Ritz finalisation, against the library's
+    FP64 path (parity-tested against the FP64 oracle) on (a) the BF16-stored
+    values and (b) the original FP64 matrix, same schedule and start: sin theta
+    between the final subspaces and the largest relative Ritz-value error."""
+    dev = w.A.device
+
+    def run(Pr):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lp.lp_run(Pr, w.k, sched, w.mode, w.Y0, ritz=True)
+        torch.cuda.synchronize()
+        return r["Z"], r["ritz"].to("cpu").numpy(), time.perf_counter() - t0
+
+    runs = {}
+    log("precision: BF16 storage, BF16 operands (fused kernel)")
+    runs["bf16_storage_bf16_operands"] = run(P)
+    log("precision: BF16 storage, FP32 operands (two-pass kernel)")
+    lp.lp_set_tuning(P, 1, tuning["chunk_rows"])
+    runs["bf16_storage_fp32_operands"] = run(P)
+    lp.lp_set_tuning(P, tuning["local_kernel"], tuning["chunk_rows"], tuning["cached_loads"])
+    log("precision: FP64 on the BF16-stored values")
+    A64 = w.A.to(torch.float64)
+    P64 = lp.lp_create(A64, w.offsets, w.k)
+    runs["fp64_on_bf16_values"] = run(P64)
+    del P64, A64
+    torch.cuda.empty_cache()
+    log("precision: FP32 storage")
+    w32 = synth.make_bf16_1048576x2048(device=dev, dtype=torch.float32)
+    P32 = lp.lp_create(w32.A, w32.offsets, w32.k)
+    lp.lp_autotune(P32, w32.k)
+    runs["fp32_storage"] = run(P32)
+    del P32, w32
+    torch.cuda.empty_cache()
+    log("precision: FP64 original matrix")
+    w64 = synth.make_bf16_1048576x2048(device=dev, dtype=torch.float64)
+    P64 = lp.lp_create(w64.A, w64.offsets, w64.k)
+    ref = run(P64)
+    del P64, w64
+    torch.cuda.empty_cache()
+    ref_b = runs["fp64_on_bf16_values"]
+    out = {"reference": "library FP64 path, same schedule, start and Ritz finalisation",
+           "fp64_original_s_per_run": round(ref[2], 3)}
+    for name, (Z, ritz, sec) in runs.items():
+        rec = {"s_per_run": round(sec, 3),
+               "sin_vs_fp64_original": lp.lp_sin_theta(Z, ref[0]),
+               "ritz_rel_err_vs_fp64_original": float(np.max(np.abs(ritz - ref[1]) / np.abs(ref[1])))}
+        if name.startswith("bf16"):
+            rec["sin_vs_fp64_same_values"] = lp.lp_sin_theta(Z, ref_b[0])
+        out[name] = rec
+    return out
+
+
 def rounds_to(hist, thresholds=(1e-1, 1e-2, 1e-3, 1e-6)):
     out = {}
     for th in thresholds:
@@ -249,6 +303,8 @@ def main():
     ap.add_argument("--mode", default=None, choices=["sign", "opt", "vanilla"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--precision", action="store_true",
+                    help="bf16 workload: both operand modes and both storage forms against FP64 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the m LocalPower nodes are partitions on a single "
@@ -341,6 +397,8 @@ def main():
     if not args.no_convergence and args.workload == "fp32-262144x1024":
         log("convergence (rounds to sin theta thresholds)")
         out["convergence"] = convergence(lp, P, w, k)
+    if args.precision and args.workload == "bf16-1048576x2048":
+        out["precision"] = precision_report(lp, synth, w, P, tuning, sched)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(w)
