@@ -98,8 +98,10 @@ lp_status lp_destroy(lp_problem* P);
  *                 product 1 of the next), eight waves; 5 pipelined, four waves; 6 eight
  *                 waves with the next two tiles in flight (deeper prefetch); 7 direct-to-LDS
  *                 tile loads (eight waves at d = 1024, else four); 8 direct-to-LDS, four
- *                 waves.  The eight-wave forms need d in {512, 1024} (else they run with
- *                 four waves).
+ *                 waves; 9 direct-to-LDS and software-pipelined (product 2 of one tile
+ *                 overlapping the operand reads of the next; eight waves at d = 1024,
+ *                 else four).  The eight-wave forms need d in {512, 1024} (else they run
+ *                 with four waves).
  *                 BF16 A (k in {16, 32}, d in {512, 1024, 1536, 2048}; Z and t rounded to
  *                 BF16 as operands): 2 four waves; 3 eight waves (d in {1024, 2048}).
  *                 Other shapes and ranks use the two-pass kernel.

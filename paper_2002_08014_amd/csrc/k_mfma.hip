@@ -457,6 +457,174 @@ k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restric
     for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
 }
 
+// Software-pipelined direct-to-LDS form.  Per tile j: the operands of both
+// products are read from the tile buffer while no tile load is in flight (plain
+// LDS loads, waited for at first use), product 2 of tile j - 1 runs on the
+// operands and t kept in registers from the previous step while those reads
+// land, then the load of tile j + 1 starts and product 1 of tile j follows; the
+// per-wave t partials go through a double-buffered LDS array, so one block
+// barrier per tile suffices (a wave overwrites a t buffer only after the
+// barrier that every wave reaches after reading it).
+template <int NQ, int W, int AUX>
+__global__ void __launch_bounds__(64 * W, 1)
+k1_mfma_f32_dmap(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
+                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+  constexpr int D = 16 * NQ * W;
+  constexpr int S = 16 * NQ;            // columns per wave slice
+  constexpr int RB = 4 * S;             // bytes per slice row
+  constexpr int TB = kTileRows * RB;    // bytes per wave tile
+  constexpr int NI = TB / 1024;         // 1 KB direct-to-LDS loads per wave tile
+  static_assert(NQ % 4 == 0 && TB % 1024 == 0, "slice rows must be whole 256-byte groups");
+  __shared__ __attribute__((aligned(16))) unsigned char abuf[2][W][TB];
+  __shared__ f4 tpart[2][W][64];
+
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane >> 4;
+  const int i = lane & 15;
+  const int slice0 = w * S;
+  const int rows = (int)it.rows;
+  const int ntiles = (rows + kTileRows - 1) / kTileRows;
+  const float* Ab = A + it.row0 * lda + slice0;
+
+  int32_t loff[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int byte = ii * 1024 + 16 * lane;
+    const int r = byte / RB;
+    const int p = (byte % RB) / 16;
+    loff[ii] = r * (int32_t)lda + 4 * (p ^ ((r ^ (p >> 4)) & 15));
+  }
+  auto issue = [&](int r0, int b) {
+    if (r0 + kTileRows <= rows) {
+      const float* base = Ab + (int64_t)r0 * lda;
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii)
+        __builtin_amdgcn_global_load_lds((const void*)(base + loff[ii]),
+                                         (lds_void*)&abuf[b][w][ii * 1024], 16, 0, AUX);
+    } else {
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii) {
+        const int byte = ii * 1024 + 16 * lane;
+        const int r = byte / RB;
+        const int p = (byte % RB) / 16;
+        const int row = min(r0 + r, rows - 1);
+        const float* src = Ab + (int64_t)row * lda + 4 * (p ^ ((r ^ (p >> 4)) & 15));
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)&abuf[b][w][ii * 1024], 16, 0,
+                                         AUX);
+      }
+    }
+  };
+  issue(0, 0);
+
+  const float* Z = Zw + (int64_t)it.part * z_stride;
+  float zr[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+  f4 acc[NQ];
+#pragma unroll
+  for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // product 2 of a tile: acc += A_tile^T t (operands a2, t as in k1_mfma_f32_dma)
+  auto product2 = [&](const f4 (&a2)[NQ], const f4& t, int st0, int st1) {
+#pragma unroll
+    for (int st = st0; st < st1; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[4 * cq + c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[st][c], t[s], acc[4 * cq + c], 0, 0, 0);
+    }
+  };
+
+  f4 a2p[NQ];
+  f4 tprev = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) a2p[q] = tprev;
+  for (int j = 0; j < ntiles; ++j) {
+    const int b = j & 1;
+    wait_vm_all();   // tile j has landed; no tile load is in flight now
+    const unsigned char* tbp = &abuf[b][w][0];
+    f4 a1[NQ], a2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a1[q] = *(const f4*)(tbp + i * RB + 16 * dpos(i, 4 * q + g));
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+      const int r = 4 * g + s;
+      a2[st] = *(const f4*)(tbp + r * RB + 16 * dpos(r, (NQ / 4) * i + cq));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // product 2 of the previous tile (zero operands at j = 0) while the reads land
+    product2(a2p, tprev, 0, NQ / 2);
+    __builtin_amdgcn_sched_barrier(0);
+    if (j + 1 < ntiles) issue((j + 1) * kTileRows, b ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+    product2(a2p, tprev, NQ / 2, NQ);
+    // product 1 of this tile: four accumulation chains
+    f4 tw[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tw[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        tw[(2 * q + (c >> 1)) & 3] =
+            __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q][c], zr[q][c], tw[(2 * q + (c >> 1)) & 3], 0, 0, 0);
+    tpart[b][w][lane] = (tw[0] + tw[1]) + (tw[2] + tw[3]);
+    lds_barrier();
+    // the W partials (asm reads: the compiler would otherwise wait for the tile
+    // load just issued before reading LDS)
+    static_assert(W % 4 == 0, "t partials are read four at a time");
+    f4 tv[W];
+    const unsigned tp0 = lds_addr(&tpart[b][0][lane]);
+#pragma unroll
+    for (int v = 0; v < W; v += 4)
+      lds_read4(tv[v], tv[v + 1], tv[v + 2], tv[v + 3], tp0 + 1024 * v, tp0 + 1024 * (v + 1),
+                tp0 + 1024 * (v + 2), tp0 + 1024 * (v + 3));
+    f4 t = tv[0];
+#pragma unroll
+    for (int v = 1; v < W; ++v) t += tv[v];
+    const int valid = rows - j * kTileRows;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * g + r >= valid) t[r] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a2p[q] = a2[q];
+    tprev = t;
+  }
+  product2(a2p, tprev, 0, NQ);
+  float* o = part + (int64_t)it.slot * D * 16;
+#pragma unroll
+  for (int h = 0; h < NQ; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+}
+
+template <int NQ, int W, int AUX>
+hipError_t launch_dmap_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
+                          const WorkItem* items, float* o, hipStream_t s) {
+  if constexpr (16 * NQ * W <= 1024 && NQ % 4 == 0 && NQ <= 8) {
+    k1_mfma_f32_dmap<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int W, int AUX>
+hipError_t launch_f32_dmap(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
+                           int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+  switch (d / (16 * W)) {
+    case 4: return launch_dmap_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 8: return launch_dmap_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int NQ, int W, int AUX>
 hipError_t launch_dma_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
                          const WorkItem* items, float* o, hipStream_t s) {
@@ -536,7 +704,8 @@ bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
 
 // Variants: 0: 4 waves, 1 WG/CU; 1: 8 waves, 1 WG/CU; 2: pipelined, 8 waves;
 // 3: pipelined, 4 waves; 4: 8 waves with two tiles in flight; 5: direct-to-LDS tile
-// loads (8 waves at d = 1024, else 4); 6: direct-to-LDS, 4 waves.  The 8-wave forms need d in {512, 1024} (else 4 waves).
+// loads (8 waves at d = 1024, else 4); 6: direct-to-LDS, 4 waves; 7: direct-to-LDS,
+// software-pipelined (8 waves at d = 1024, else 4).  The 8-wave forms need d in {512, 1024} (else 4 waves).
 template <bool NT>
 hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, const float* z,
                         int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
@@ -562,6 +731,15 @@ hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, 
     case 6: {
       // direct-to-LDS form with four waves (one per SIMD, 512 registers each)
       constexpr int AUX = NT ? 2 : 0;
+      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    }
+    case 7: {
+      // software-pipelined direct-to-LDS form with 64- or 128-column slices (eight
+      // waves at d = 1024, four at d = 256 and 512); the plain form at d = 768
+      constexpr int AUX = NT ? 2 : 0;
+      if (P.d == 1024) return launch_f32_dmap<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (P.d == 256 || P.d == 512)
+        return launch_f32_dmap<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
       return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
     }
     default: return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);

@@ -715,7 +715,7 @@ lp_status lp_destroy(lp_problem* P) {
 lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
     return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
-  if (t->local_kernel < 0 || t->local_kernel > 8) return fail(LP_EINVAL, "local_kernel out of range");
+  if (t->local_kernel < 0 || t->local_kernel > 9) return fail(LP_EINVAL, "local_kernel out of range");
   if (t->local_kernel > 3 && fused_kind(P) == LocalPath::MfmaBf16)
     return fail(LP_EINVAL, "the BF16 fused kernel has two variants (local_kernel 2, 3)");
   int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
@@ -816,7 +816,7 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
     return LP_OK;
   }
   const bool fused_ok = fused_for_k(P, k);
-  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 8 : 3;
+  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 9 : 3;
   std::vector<lp_tuning> cand;
   const int64_t c0 = P->plan.min_chunk_rows;
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
