@@ -23,6 +23,14 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kBM = 128;   // output rows (pass 1) or columns (pass 2) per workgroup
 constexpr int kBK = 32;    // contraction slice staged per step
 
+// LDS row strides (floats) of the staged operands.  A lane reads element
+// [4 kk + l/16][16 nt + l%16] of a k-wide operand (or of the 128-wide A slice
+// in pass 2): a stride of 16 modulo 64 words puts the 64 lanes on 64 distinct
+// banks (16 (l/16) + l%16).  Pass 1 reads A as [16 mt + l%16][4 kk + l/16]:
+// its stride 36 (16-byte aligned rows) gives 36 (l%16) + l/16, distinct
+// modulo 64.
+constexpr int pad16(int n) { return n <= 16 ? 16 : 80; }   // n <= 64
+
 template <typename TA>
 __device__ inline f4 load4(const TA* p);
 template <>
@@ -43,7 +51,7 @@ tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
            int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ t) {
   constexpr int N = 16 * NT;
   constexpr int AP = kBK + 4;            // padded A row (floats)
-  constexpr int ZP = N + 4;              // padded Z row
+  constexpr int ZP = pad16(N);           // padded Z row
   constexpr int ZE = (kBK * N) / 256;    // Z elements per thread per slice
   __shared__ float As[2][kBM * AP];
   __shared__ float Zs[2][kBK * ZP];
@@ -131,8 +139,8 @@ __global__ void __launch_bounds__(256)
 ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ t,
            const WorkItem* __restrict__ items, float* __restrict__ part) {
   constexpr int N = 16 * NT;
-  constexpr int AP = kBM + 4;            // padded A slice row (floats)
-  constexpr int TP = N + 4;
+  constexpr int AP = kBM + 16;           // padded A slice row (floats)
+  constexpr int TP = pad16(N);
   constexpr int TE = (kBK * N) / 256;
   __shared__ float As[2][kBK * AP];
   __shared__ float Ts[2][kBK * TP];
