@@ -664,9 +664,7 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
   P->user_stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking);
-  for (hipEvent_t* ev : {&P->ev_fork, &P->ev_join2, &P->ev_base, &P->ev_k1[0], &P->ev_k1[1]})
-    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join_out, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreate(&P->ev_t0);
@@ -905,6 +903,21 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   const bool hist = o.U_ref != nullptr && o.sin_hist != nullptr;
   if (o.time_local < 0 || o.time_local > 2) return fail(LP_EINVAL, "time_local must be 0, 1 or 2");
   if (o.split_rounds < 0 || o.split_rounds > 2) return fail(LP_EINVAL, "split_rounds must be 0, 1 or 2");
+  bool split;
+  {
+    const bool fused =
+        (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, P->d, P->lda, k)) ||
+        (P->plan.path == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, P->d, P->lda, k, P->A));
+    split = P->can_split && (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
+  }
+  if (split && P->stream2 == nullptr) {
+    // the second stream and its events exist only in problems that run split
+    // rounds (an idle stream still takes a hardware queue slot from the others)
+    hipError_t e = hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&P->ev_fork, &P->ev_join2, &P->ev_base, &P->ev_k1[0], &P->ev_k1[1]})
+      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(LP_EDEVICE, std::string("second stream/events: ") + hipGetErrorString(e));
+  }
   const bool timing = o.time_local != 0;
   P->timing_first_only = o.time_local == 2;
   const bool graph = o.use_graph != 0;
@@ -934,12 +947,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   LP_HIP(hipEventRecord(P->ev_t0, s));
   int rounds = 0, iters = 0, hist_done = 0, graph_rounds = 0;
   P->timing = timing;
-  {
-    const bool fused = (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, d, P->lda, k)) ||
-                       (P->plan.path == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, d, P->lda, k, P->A));
-    P->split_now = P->can_split && (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
-  }
-  const bool split = P->split_now;
+  P->split_now = split;
   std::vector<std::pair<int, int>> pending;  // (slot, p) of timed graph rounds not yet harvested
   for (int r = 0; r < T; ++r) {
     const int p = p_sched[r];
