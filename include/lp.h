@@ -100,10 +100,12 @@ lp_status lp_destroy(lp_problem* P);
  *                 tile loads (eight waves at d = 1024, else four); 8 direct-to-LDS, four
  *                 waves; 9 direct-to-LDS and software-pipelined (product 2 of one tile
  *                 overlapping the operand reads of the next; eight waves at d = 1024,
- *                 else four).  The eight-wave forms need d in {512, 1024} (else they run
+ *                 else four); 10 direct-to-LDS with two tiles in flight per wave (eight
+ *                 waves at d = 1024, else four).  The eight-wave forms need d in {512, 1024} (else they run
  *                 with four waves).
  *                 BF16 A (k in {16, 32}, d in {512, 1024, 1536, 2048}; Z and t rounded to
- *                 BF16 as operands): 2 four waves; 3 eight waves (d in {1024, 2048}).
+ *                 BF16 as operands): 2 four waves; 3 eight waves (d in {1024, 2048});
+ *                 4 and 5 the same with two tiles in flight per wave.
  *                 Other shapes and ranks use the two-pass kernel.
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
  *                 default chosen at lp_create, which sized the workspace); 0 = default.

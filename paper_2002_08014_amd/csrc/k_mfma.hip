@@ -334,6 +334,11 @@ __device__ inline void lds_read4(f4& x0, f4& x1, f4& x2, f4& x3, unsigned a0, un
 // direct-to-LDS loads included); also a compiler barrier.
 __device__ inline void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Wait until at most N global memory operations of this wave are outstanding
+// (they complete in issue order).
+template <int N>
+__device__ inline void wait_vm_n() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory"); }
+
 template <int NQ, int W, int AUX>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
@@ -604,6 +609,167 @@ k1_mfma_f32_dmap(const float* __restrict__ A, int64_t lda, const float* __restri
     for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
 }
 
+// Direct-to-LDS form with two tiles in flight per wave.  Once a tile's
+// operands of both products are in registers (asm reads that wait inside),
+// its buffer is refilled with the tile two ahead, so the other buffer's load
+// and this one overlap: twice the bytes in flight of the other forms at the
+// same LDS size.  Measured without any matrix-core work, the one-tile-ahead
+// forms take as long as their loads' latency allows at 64 KB in flight per CU.
+template <int NQ, int W, int AUX>
+__global__ void __launch_bounds__(64 * W, 1)
+k1_mfma_f32_dma2(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
+                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+  constexpr int D = 16 * NQ * W;
+  constexpr int S = 16 * NQ;            // columns per wave slice
+  constexpr int RB = 4 * S;             // bytes per slice row
+  constexpr int TB = kTileRows * RB;    // bytes per wave tile
+  constexpr int NI = TB / 1024;         // 1 KB direct-to-LDS loads per wave tile
+  static_assert(NQ % 4 == 0 && TB % 1024 == 0, "slice rows must be whole 256-byte groups");
+  __shared__ __attribute__((aligned(16))) unsigned char abuf[2][W][TB];
+  __shared__ f4 tpart[2][W][64];
+
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane >> 4;
+  const int i = lane & 15;
+  const int slice0 = w * S;
+  const int rows = (int)it.rows;
+  const int ntiles = (rows + kTileRows - 1) / kTileRows;
+  const float* Ab = A + it.row0 * lda + slice0;
+
+  int32_t loff[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int byte = ii * 1024 + 16 * lane;
+    const int r = byte / RB;
+    const int p = (byte % RB) / 16;
+    loff[ii] = r * (int32_t)lda + 4 * (p ^ ((r ^ (p >> 4)) & 15));
+  }
+  auto issue = [&](int r0, int b) {
+    if (r0 + kTileRows <= rows) {
+      const float* base = Ab + (int64_t)r0 * lda;
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii)
+        __builtin_amdgcn_global_load_lds((const void*)(base + loff[ii]),
+                                         (lds_void*)&abuf[b][w][ii * 1024], 16, 0, AUX);
+    } else {
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii) {
+        const int byte = ii * 1024 + 16 * lane;
+        const int r = byte / RB;
+        const int p = (byte % RB) / 16;
+        const int row = min(r0 + r, rows - 1);
+        const float* src = Ab + (int64_t)row * lda + 4 * (p ^ ((r ^ (p >> 4)) & 15));
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)&abuf[b][w][ii * 1024], 16, 0,
+                                         AUX);
+      }
+    }
+  };
+
+  const float* Z = Zw + (int64_t)it.part * z_stride;
+  float zr[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+  f4 acc[NQ];
+#pragma unroll
+  for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
+  // the Z loads were issued first, so the in-order count below covers them too
+  issue(0, 0);
+  if (ntiles > 1) issue(kTileRows, 1);
+
+  for (int j = 0; j < ntiles; ++j) {
+    const int b = j & 1;
+    // tile j complete; tile j + 1 (issued after it) may still be in flight
+    if (j + 1 < ntiles)
+      wait_vm_n<NI>();
+    else
+      wait_vm_all();
+    const unsigned tb = lds_addr(&abuf[b][w][0]);
+    unsigned ad1[NQ], ad2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ad1[q] = tb + i * RB + 16 * dpos(i, 4 * q + g);
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+      const int r = 4 * g + s;
+      ad2[st] = tb + r * RB + 16 * dpos(r, (NQ / 4) * i + cq);
+    }
+    f4 a1[NQ], a2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q += 4)
+      lds_read4(a1[q], a1[q + 1], a1[q + 2], a1[q + 3], ad1[q], ad1[q + 1], ad1[q + 2], ad1[q + 3]);
+#pragma unroll
+    for (int q = 0; q < NQ; q += 4)
+      lds_read4(a2[q], a2[q + 1], a2[q + 2], a2[q + 3], ad2[q], ad2[q + 1], ad2[q + 2], ad2[q + 3]);
+    // this wave's part of buffer b is in registers: refill it with tile j + 2
+    if (j + 2 < ntiles) issue((j + 2) * kTileRows, b);
+    f4 tw[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tw[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        tw[(2 * q + (c >> 1)) & 3] =
+            __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q][c], zr[q][c], tw[(2 * q + (c >> 1)) & 3], 0, 0, 0);
+    tpart[b][w][lane] = (tw[0] + tw[1]) + (tw[2] + tw[3]);
+    lds_barrier();
+    static_assert(W % 4 == 0, "t partials are read four at a time");
+    f4 tv[W];
+    const unsigned tp0 = lds_addr(&tpart[b][0][lane]);
+#pragma unroll
+    for (int v = 0; v < W; v += 4)
+      lds_read4(tv[v], tv[v + 1], tv[v + 2], tv[v + 3], tp0 + 1024 * v, tp0 + 1024 * (v + 1),
+                tp0 + 1024 * (v + 2), tp0 + 1024 * (v + 3));
+    f4 t = tv[0];
+#pragma unroll
+    for (int v = 1; v < W; ++v) t += tv[v];
+    const int valid = rows - j * kTileRows;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * g + r >= valid) t[r] = 0.f;
+#pragma unroll
+    for (int st = 0; st < NQ; ++st) {
+      const int s = st / (NQ / 4), cq = st % (NQ / 4);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[4 * cq + c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[st][c], t[s], acc[4 * cq + c], 0, 0, 0);
+    }
+  }
+  float* o = part + (int64_t)it.slot * D * 16;
+#pragma unroll
+  for (int h = 0; h < NQ; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+}
+
+template <int NQ, int W, int AUX>
+hipError_t launch_dma2_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
+                          const WorkItem* items, float* o, hipStream_t s) {
+  if constexpr (16 * NQ * W <= 1024 && NQ % 4 == 0) {
+    k1_mfma_f32_dma2<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int W, int AUX>
+hipError_t launch_f32_dma2(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
+                           int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+  switch (d / (16 * W)) {
+    case 4: return launch_dma2_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 8: return launch_dma2_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 12: return launch_dma2_nq<12, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 16: return launch_dma2_nq<16, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int NQ, int W, int AUX>
 hipError_t launch_dmap_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
                           const WorkItem* items, float* o, hipStream_t s) {
@@ -705,7 +871,8 @@ bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
 // Variants: 0: 4 waves, 1 WG/CU; 1: 8 waves, 1 WG/CU; 2: pipelined, 8 waves;
 // 3: pipelined, 4 waves; 4: 8 waves with two tiles in flight; 5: direct-to-LDS tile
 // loads (8 waves at d = 1024, else 4); 6: direct-to-LDS, 4 waves; 7: direct-to-LDS,
-// software-pipelined (8 waves at d = 1024, else 4).  The 8-wave forms need d in {512, 1024} (else 4 waves).
+// software-pipelined (8 waves at d = 1024, else 4); 8: direct-to-LDS with two tiles in
+// flight per wave (8 waves at d = 1024, else 4).  The 8-wave forms need d in {512, 1024} (else 4 waves).
 template <bool NT>
 hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, const float* z,
                         int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
@@ -741,6 +908,12 @@ hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, 
       if (P.d == 256 || P.d == 512)
         return launch_f32_dmap<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
       return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    }
+    case 8: {
+      // direct-to-LDS with two tiles in flight per wave (8 waves at d = 1024, else 4)
+      constexpr int AUX = NT ? 2 : 0;
+      if (P.d == 1024) return launch_f32_dma2<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      return launch_f32_dma2<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
     }
     default: return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
   }

@@ -95,9 +95,16 @@ __device__ inline void lds_read4_tr(s4& x0, s4& x1, s4& x2, s4& x3, unsigned a0,
 // direct-to-LDS loads included); also a compiler barrier.
 __device__ inline void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Wait until at most N global memory operations of this wave are outstanding
+// (they complete in issue order).
+template <int N>
+__device__ inline void wait_vm_n() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory"); }
+
 // W: waves; NC: 32-column chunks per wave slice (d = 32 NC W); KT: 16-wide k
-// blocks (k = 16 KT); AUX: cache policy of the A loads (0 default, 2 nontemporal).
-template <int W, int NC, int KT, int AUX>
+// blocks (k = 16 KT); AUX: cache policy of the A loads (0 default, 2 nontemporal);
+// AHEAD: two tiles in flight per wave (a buffer is refilled with the tile two
+// ahead as soon as this wave's last read of it is done) instead of one.
+template <int W, int NC, int KT, int AUX, bool AHEAD>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
              int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
@@ -137,6 +144,9 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     }
   };
   issue(0, 0);
+  if constexpr (AHEAD) {
+    if (ntiles > 1) issue(kRows, 1);
+  }
 
   // Z_i slice in B-operand layout: zb[c][kt][e] = Z[slice0 + 32c + 8g + e][16kt + i]
   const float* Z = Zw + (int64_t)it.part * z_stride;
@@ -171,8 +181,16 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     // tile j was issued one iteration ago: wait for it (a full wait, so no other
     // memory operation the compiler placed in between can satisfy the count),
     // then start tile j + 1 into the other buffer; it lands while tile j computes
-    wait_vm_all();
-    if (j + 1 < ntiles) issue((j + 1) * kRows, b ^ 1);
+    if constexpr (AHEAD) {
+      // tile j complete; tile j + 1 (issued after it) may still be in flight
+      if (j + 1 < ntiles)
+        wait_vm_n<NI>();
+      else
+        wait_vm_all();
+    } else {
+      wait_vm_all();
+      if (j + 1 < ntiles) issue((j + 1) * kRows, b ^ 1);
+    }
     const unsigned tb = lds_addr(&abuf[b][w][0]);
 
     // product 1: partial t over this wave's slice (two chains per k block)
@@ -230,6 +248,10 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
           yacc[c0 + c][kt] =
               __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[c], tb_op[kt], yacc[c0 + c][kt], 0, 0, 0);
     }
+    if constexpr (AHEAD) {
+      // this wave's reads of buffer b are done (the asm reads wait inside)
+      if (j + 2 < ntiles) issue((j + 2) * kRows, b);
+    }
   }
   // yacc[ct][kt][r] = Y[slice0 + 16ct + 4g + r][16kt + i]
   float* o = part + (int64_t)it.slot * D * K;
@@ -242,30 +264,41 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
         o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * K + 16 * kt + i] = yacc[ct][kt][r];
 }
 
-template <int W, int NC, int KT>
+template <int W, int NC, int KT, bool AHEAD>
 hipError_t launch_nc(int nitems, bool nt, const uint16_t* a, int64_t lda, const float* z,
                      int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
   if (nt)
-    k1_mfma_bf16<W, NC, KT, 2><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_bf16<W, NC, KT, 2, AHEAD><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
   else
-    k1_mfma_bf16<W, NC, KT, 0><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_bf16<W, NC, KT, 0, AHEAD><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
   return hipGetLastError();
 }
 
-// variant 0: four waves (any eligible d); variant 1: eight waves (d = 1024 or 2048)
+template <int KT, bool AHEAD>
+hipError_t launch_kt_ahead(int64_t d, bool w8, int nitems, bool nt, const uint16_t* a, int64_t lda,
+                           const float* z, int64_t z_stride, const WorkItem* items, float* o,
+                           hipStream_t s) {
+  if (w8 && d == 1024) return launch_nc<8, 4, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  if (w8 && d == 2048) return launch_nc<8, 8, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  switch (d) {
+    case 512: return launch_nc<4, 4, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 1024: return launch_nc<4, 8, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 1536: return launch_nc<4, 12, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 2048: return launch_nc<4, 16, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// variant 0: four waves (any eligible d); 1: eight waves (d = 1024 or 2048);
+// 2, 3: the same with two tiles in flight per wave
 template <int KT>
 hipError_t launch_kt(int64_t d, int variant, int nitems, bool nt, const uint16_t* a, int64_t lda,
                      const float* z, int64_t z_stride, const WorkItem* items, float* o,
                      hipStream_t s) {
-  if (variant == 1 && d == 1024) return launch_nc<8, 4, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-  if (variant == 1 && d == 2048) return launch_nc<8, 8, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-  switch (d) {
-    case 512: return launch_nc<4, 4, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 1024: return launch_nc<4, 8, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 1536: return launch_nc<4, 12, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 2048: return launch_nc<4, 16, KT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    default: return hipErrorInvalidValue;
-  }
+  const bool w8 = variant == 1 || variant == 3;
+  if (variant >= 2)
+    return launch_kt_ahead<KT, true>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
+  return launch_kt_ahead<KT, false>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
 }
 
 }  // namespace

@@ -713,9 +713,9 @@ lp_status lp_destroy(lp_problem* P) {
 lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
     return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
-  if (t->local_kernel < 0 || t->local_kernel > 9) return fail(LP_EINVAL, "local_kernel out of range");
-  if (t->local_kernel > 3 && fused_kind(P) == LocalPath::MfmaBf16)
-    return fail(LP_EINVAL, "the BF16 fused kernel has two variants (local_kernel 2, 3)");
+  if (t->local_kernel < 0 || t->local_kernel > 10) return fail(LP_EINVAL, "local_kernel out of range");
+  if (t->local_kernel > 5 && fused_kind(P) == LocalPath::MfmaBf16)
+    return fail(LP_EINVAL, "the BF16 fused kernel has four variants (local_kernel 2 to 5)");
   int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
   if (cr % 16 != 0 || cr < P->plan.min_chunk_rows)
     return fail(LP_EINVAL, "chunk_rows must be a multiple of 16 and >= the default");
@@ -732,8 +732,10 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
     P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 1;
   } else if (fk == LocalPath::MfmaBf16) {
     P->plan.path = fk;
-    const bool w8 = P->d == 1024 || P->d == 2048;   // the eight-wave form needs these widths
-    P->plan.variant = (t->local_kernel == 3 && w8) ? 1 : 0;
+    const bool w8 = P->d == 1024 || P->d == 2048;   // the eight-wave forms need these widths
+    const bool ahead = t->local_kernel >= 4;        // two tiles in flight per wave
+    const bool eight = (t->local_kernel == 3 || t->local_kernel == 5) && w8;
+    P->plan.variant = (ahead ? 2 : 0) + (eight ? 1 : 0);
   }
   P->plan.nt_loads = t->cached_loads == 0;
   build_items(&P->plan, P->offsets.data(), cr);
@@ -814,7 +816,7 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
     return LP_OK;
   }
   const bool fused_ok = fused_for_k(P, k);
-  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 9 : 3;
+  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 10 : 5;
   std::vector<lp_tuning> cand;
   const int64_t c0 = P->plan.min_chunk_rows;
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {

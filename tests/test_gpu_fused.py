@@ -12,7 +12,7 @@ from tests._util import host, sin_theta_np, upcast
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = (1, 2, 3, 4, 5, 6, 7, 8, 9)   # two-pass, then the fused forms (see lp_tuning)
+VARIANTS = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10)   # two-pass, then the fused forms (see lp_tuning)
 
 
 @pytest.fixture(scope="module")
@@ -111,7 +111,7 @@ def test_autotune_applies_a_valid_choice(lp, tmp_path):
     P = lp.lp_create(A_dev, w.offsets, 16)
     cache = str(tmp_path / "tune.txt")
     t = lp.lp_autotune(P, 16, cache)
-    assert 2 <= t["local_kernel"] <= 9 and t["chunk_rows"] % 16 == 0
+    assert 2 <= t["local_kernel"] <= 10 and t["chunk_rows"] % 16 == 0
     assert lp.lp_get_tuning(P)["local_kernel"] == t["local_kernel"]
     assert open(cache).read().count("=") == 1
     P2 = lp.lp_create(A_dev, w.offsets, 16)

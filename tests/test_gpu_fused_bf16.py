@@ -42,7 +42,7 @@ def _check(Y, A, offsets, Zw, parts):
 
 
 @pytest.mark.parametrize("cached", [False, True])
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 @pytest.mark.parametrize("k", [16, 32])
 @pytest.mark.parametrize("d", [512, 1024, 1536, 2048])
 def test_bf16_fused_small(lp, d, k, variant, cached):
@@ -54,7 +54,7 @@ def test_bf16_fused_small(lp, d, k, variant, cached):
     lp.lp_set_tuning(P, variant, 0, cached)
     t = lp.lp_get_tuning(P)
     w8 = d in (1024, 2048)
-    assert t["local_kernel"] == (variant if (variant == 2 or w8) else 2)
+    assert t["local_kernel"] == (variant if (variant in (2, 4) or w8) else variant - 1)
     assert t["cached_loads"] == cached
     Z = oracle.orth(np.random.default_rng(d + k).standard_normal((d, k)))
     Y = host(lp.lp_local_multiply(P, k, torch.as_tensor(Z)))
@@ -65,7 +65,7 @@ def test_bf16_fused_rejects_extra_variants(lp):
     w = synth.make_small(2048, 512, 16, 2, seed=1, dtype=torch.bfloat16)
     P = lp.lp_create(w.A.to("cuda:0"), w.offsets, 16)
     with pytest.raises(RuntimeError):
-        lp.lp_set_tuning(P, 4, 0)
+        lp.lp_set_tuning(P, 6, 0)
 
 
 def test_bf16_other_k_falls_back(lp):
@@ -90,7 +90,7 @@ def bf16_wide(lp):
     return synth.make_bf16_1048576x2048(device="cuda:0")
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_bf16_fused_full_size_sampled(lp, bf16_wide, variant):
     """Precision-form shape (64 partitions of 16384 x 2048, k = 32), the launch
     configuration the benchmark times: three sampled partitions."""
