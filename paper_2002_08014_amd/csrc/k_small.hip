@@ -202,85 +202,127 @@ __device__ __forceinline__ void chol_inv_wave(const double* G, double* Ri, int k
   __syncthreads();
 }
 
-// The same for any k <= 64 by the whole block (kBlock threads) in LDS: G is
-// overwritten.  Right-looking elimination on the upper triangle with one block
-// barrier per step (the pivot row is read, only rows below it are written):
-// after it row j holds the pivot d_j and the unscaled row, and
-// R[j][c] = G[j][c] / sqrt(d_j).  The inverse solves R X = I the same way from
-// the last row up: X[i][c] = B[i][c] / R[i][i], and every row r < i subtracts
-// R[r][i] X[i][c].  *bad and the identity on breakdown as above.
-__device__ __forceinline__ void chol_inv_block(double* G, double* Ri, int k, int* bad) {
-  __shared__ double rs[kMaxK];   // 1 / sqrt(d_j)
-  __shared__ int badl;
-  const int t = threadIdx.x;
-  const int c = t & 63, r0 = t >> 6;
-  constexpr int kRowStep = kBlock / 64;
-  if (t == 0) badl = 0;
-  for (int j = 0; j < k; ++j) {
-    __syncthreads();   // row j is final
-    double djj = G[j * k + j];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      djj = 1.0;
-      if (t == 0) badl = 1;
+// Cholesky S = R^T R of the 16 x 16 LDS block S (row stride ld) and X = R^{-1},
+// by the first wavefront (the column-per-lane form above without padding; lanes
+// 16..63 repeat lanes 0..15).  R and X are written with row stride ld, zero
+// below the diagonal.  A non-positive or non-finite pivot sets *bad and is taken
+// as 1.  No barrier inside.
+__device__ __forceinline__ void chol16_wave(const double* S, double* R, double* X, int ld, int* bad) {
+  if (threadIdx.x < 64) {
+    const int c = threadIdx.x & 15;
+    double g[16], r[16], rd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) g[i] = S[i * ld + c];
+    bool badw = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      double djj = rdlane(g[j], j);
+      const bool ok = djj > 0.0 && isfinite(djj);
+      badw = badw || !ok;
+      djj = ok ? djj : 1.0;
+      const double inv = rsqrt_pos(djj);
+      rd[j] = inv;
+      const double rjc = (c == j) ? djj * inv : (c > j ? g[j] * inv : 0.0);
+      r[j] = rjc;
+#pragma unroll
+      for (int i = j + 1; i < 16; ++i) g[i] = fma(-rdlane(rjc, i), rjc, g[i]);
     }
-    const double inv = 1.0 / djj;
-    if (c > j && c < k) {
-      // rows i = j + 1 + r0 + 4q <= c of column c: all loads first, then the updates
-      const double gjc = G[j * k + c] * inv;
-      double a[kMaxK / kRowStep], v[kMaxK / kRowStep];
 #pragma unroll
-      for (int q = 0; q < kMaxK / kRowStep; ++q) {
-        const int i = min(j + 1 + r0 + kRowStep * q, c);
-        a[q] = G[j * k + i];
-        v[q] = G[i * k + c];
-      }
+    for (int i = 15; i >= 0; --i) {
+      double acc = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-      for (int q = 0; q < kMaxK / kRowStep; ++q) {
-        const int i = j + 1 + r0 + kRowStep * q;
-        if (i <= c) G[i * k + c] = fma(-a[q], gjc, v[q]);
-      }
+      for (int l = i + 1; l < 16; ++l) acc = fma(-rdlane(r[i], l), g[l], acc);
+      g[i] = acc * rd[i];
     }
-  }
-  __syncthreads();
-  if (t < k) {
-    double djj = G[t * k + t];
-    if (!(djj > 0.0) || !isfinite(djj)) djj = 1.0;
-    rs[t] = 1.0 / sqrt(djj);
-  }
-  __syncthreads();
-  // R into G (upper triangle), B = I into Ri
-  for (int e = t; e < k * k; e += kBlock) {
-    const int i = e / k, cc = e - (e / k) * k;
-    const double v = G[e];
-    G[e] = (cc > i) ? v * rs[i] : (cc == i ? 1.0 / rs[i] : 0.0);
-    Ri[e] = (cc == i) ? 1.0 : 0.0;
-  }
-  for (int i = k - 1; i >= 0; --i) {
-    __syncthreads();   // row i of B is final
-    if (c >= i && c < k) {
-      const double xic = Ri[i * k + c] * rs[i];   // 1 / R[i][i] = rs[i]
-      double a[kMaxK / kRowStep], v[kMaxK / kRowStep];
+    if (threadIdx.x < 16) {
 #pragma unroll
-      for (int q = 0; q < kMaxK / kRowStep; ++q) {
-        const int r = min(r0 + kRowStep * q, i);
-        a[q] = G[r * k + i];
-        v[q] = Ri[r * k + c];
-      }
-#pragma unroll
-      for (int q = 0; q < kMaxK / kRowStep; ++q) {
-        const int r = r0 + kRowStep * q;
-        if (r < i) Ri[r * k + c] = fma(-a[q], xic, v[q]);
+      for (int i = 0; i < 16; ++i) {
+        R[i * ld + c] = r[i];
+        X[i * ld + c] = g[i];
       }
     }
+    if (threadIdx.x == 0 && badw) *bad = 1;
+  }
+}
+
+// grid (batch), block kBlock: R^{-1} of chol(sum of the Gram partials) for
+// matrix b, k <= 16 NB, by 16 x 16 blocks.  G (padded to 16 NB with the identity)
+// goes through right-looking block elimination: the diagonal block J of the
+// Schur complement is factored by chol16_wave (R_JJ and R_JJ^{-1}), then
+// R_JI = R_JJ^{-T} S_JI for I > J and S_IK -= R_JI^T R_JK for J < I <= K, each a
+// 16 x 16 product with one entry per thread.  The inverse is upper block
+// triangular: X_JJ = R_JJ^{-1} and X_IJ = -(sum_{L=I}^{J-1} X_IL R_LJ) X_JJ for
+// I < J.  On breakdown flags[b] is set and R^{-1} is the identity.
+template <int NB>
+__global__ void __launch_bounds__(kBlock)
+chol_inv_blocked_kernel(int nch, int k, const double* __restrict__ gin, double* __restrict__ rinv,
+                        int32_t* __restrict__ flags) {
+  constexpr int KM = 16 * NB;
+  __shared__ double S[KM * KM];
+  __shared__ double R[KM * KM];
+  __shared__ double X[KM * KM];
+  __shared__ int bad;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int rr = t >> 4, cc = t & 15;   // one entry of a 16 x 16 block per thread
+  const int kk = k * k;
+  if (t == 0) bad = 0;
+  for (int e = t; e < KM * KM; e += kBlock) {
+    const int i = e / KM, j = e - (e / KM) * KM;
+    S[e] = (i < k && j < k) ? sum_strided(gin + (int64_t)b * nch * kk + i * k + j, kk, nch)
+                            : (i == j ? 1.0 : 0.0);
+    R[e] = 0.0;
+    X[e] = 0.0;
   }
   __syncthreads();
-  const bool fail = badl != 0;
-  for (int e = t; e < k * k; e += kBlock) {
-    const int i = e / k, cc = e - (e / k) * k;
-    Ri[e] = fail ? (cc == i ? 1.0 : 0.0) : Ri[e] * rs[i];
+  for (int J = 0; J < NB; ++J) {
+    const int dj = 16 * J * KM + 16 * J;
+    chol16_wave(&S[dj], &R[dj], &X[dj], KM, &bad);
+    __syncthreads();
+    for (int I = J + 1; I < NB; ++I) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < 16; ++l)
+        v = fma(X[(16 * J + l) * KM + 16 * J + rr], S[(16 * J + l) * KM + 16 * I + cc], v);
+      R[(16 * J + rr) * KM + 16 * I + cc] = v;
+    }
+    __syncthreads();
+    for (int I = J + 1; I < NB; ++I)
+      for (int K = I; K < NB; ++K) {
+        double v = S[(16 * I + rr) * KM + 16 * K + cc];
+#pragma unroll
+        for (int l = 0; l < 16; ++l)
+          v = fma(-R[(16 * J + l) * KM + 16 * I + rr], R[(16 * J + l) * KM + 16 * K + cc], v);
+        S[(16 * I + rr) * KM + 16 * K + cc] = v;
+      }
+    __syncthreads();
   }
-  if (t == 0 && fail) *bad = 1;
-  __syncthreads();
+  // off-diagonal blocks of the inverse, column block by column block; the
+  // products P_IJ go to the (no longer needed) blocks S_IJ
+  for (int J = 1; J < NB; ++J) {
+    for (int I = 0; I < J; ++I) {
+      double v = 0.0;
+      for (int L = I; L < J; ++L)
+#pragma unroll
+        for (int l = 0; l < 16; ++l)
+          v = fma(X[(16 * I + rr) * KM + 16 * L + l], R[(16 * L + l) * KM + 16 * J + cc], v);
+      S[(16 * I + rr) * KM + 16 * J + cc] = v;
+    }
+    __syncthreads();
+    for (int I = 0; I < J; ++I) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < 16; ++l)
+        v = fma(-S[(16 * I + rr) * KM + 16 * J + l], X[(16 * J + l) * KM + 16 * J + cc], v);
+      X[(16 * I + rr) * KM + 16 * J + cc] = v;
+    }
+    __syncthreads();
+  }
+  const bool fail = bad != 0;
+  for (int e = t; e < kk; e += kBlock) {
+    const int i = e / k, j = e - (e / k) * k;
+    rinv[(int64_t)b * kk + e] = fail ? (i == j ? 1.0 : 0.0) : X[i * KM + j];
+  }
+  if (t == 0 && fail && flags != nullptr) flags[b] = 1;
 }
 
 // grid (nch, nb): Y_i rows of chunk c = sum of the partition's partial slots, and
@@ -326,26 +368,6 @@ aggregate_gram_kernel(int m, int64_t d, int k, const double* __restrict__ Yi, do
 
 
 
-// grid (batch), block kBlock: R^{-1} of chol(sum of the Gram partials) for
-// matrix b (all threads sum the partials, the first wavefront factors).
-template <int KM>
-__global__ void __launch_bounds__(kBlock)
-chol_inv_wave_kernel(int nch, int k, const double* __restrict__ gin, double* __restrict__ rinv,
-                     int32_t* __restrict__ flags) {
-  __shared__ double G[KM * KM];
-  __shared__ double Ri[KM * KM];
-  __shared__ int bad;
-  const int b = blockIdx.x;
-  if (threadIdx.x == 0) bad = 0;
-  sum_partials(gin, b, nch, k, G);
-  __syncthreads();
-  if constexpr (KM <= 32)
-    chol_inv_wave<KM>(G, Ri, k, &bad);
-  else
-    chol_inv_block(G, Ri, k, &bad);
-  for (int e = threadIdx.x; e < k * k; e += kBlock) rinv[(int64_t)b * k * k + e] = Ri[e];
-  if (threadIdx.x == 0 && bad && flags != nullptr) flags[b] = 1;
-}
 
 // Rows [0, rows) of Xs (row stride k) times the k x k matrix S (LDS, row stride
 // k) on FP64 matrix cores, for a tile of at most 64 rows: wave w owns rows
@@ -1003,7 +1025,7 @@ static hipError_t chol_solve_km(int batch, int64_t d, int k, int nch_in, const d
     // all of them in parallel), then factored and inverted once per matrix
     double* gsum = rfac + (int64_t)batch * k * k;
     sum_gram_kernel<<<dim3(nblk((int64_t)k * k, kBlock), batch), kBlock, 0, s>>>(nch_in, k * k, gin, gsum);
-    chol_inv_wave_kernel<KM><<<batch, kBlock, 0, s>>>(1, k, gsum, rfac, flags);
+    chol_inv_blocked_kernel<KM / 16><<<batch, kBlock, 0, s>>>(1, k, gsum, rfac, flags);
     apply_gram_kernel<TW, kc_of(KM), false><<<grid, kBlock, 0, s>>>(d, k, 0, X, rfac, Q, zw, gout,
                                                                      nullptr);
   }
