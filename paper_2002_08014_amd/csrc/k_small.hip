@@ -110,6 +110,36 @@ __device__ inline double sum_strided(const T* __restrict__ p, int64_t stride, in
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// acc[u] = sum over q < n of p[q * stride + e_u] for this thread's elements
+// e_u = threadIdx.x + u * kBlock (0 where e_u >= count), added in increasing q.
+// The loads of two steps for all EPT elements are issued together, so a
+// thread has 2 EPT loads in flight instead of one element's at a time.
+template <int EPT, typename T>
+__device__ inline void sum_rows(const T* __restrict__ p, int64_t stride, int n, int count,
+                                double (&acc)[EPT]) {
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
+  int q = 0;
+  for (; q + 1 < n; q += 2) {
+    double v0[EPT], v1[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      v0[u] = e < count ? (double)p[(int64_t)q * stride + e] : 0.0;
+      v1[u] = e < count ? (double)p[(int64_t)(q + 1) * stride + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) acc[u] = (acc[u] + v0[u]) + v1[u];
+  }
+  if (q < n) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      acc[u] += e < count ? (double)p[(int64_t)q * stride + e] : 0.0;
+    }
+  }
+}
+
 // Sum of the gram partials of batch b into an LDS k x k array (fixed order).
 __device__ void sum_partials(const double* __restrict__ part, int b, int nchunks, int k,
                              double* G) {
@@ -338,10 +368,16 @@ reduce_gram_kernel(int64_t d, int k, int b0, const TC* __restrict__ part,
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const int64_t dk = d * k;
   const int s0 = slot_off[b], s1 = slot_off[b + 1];
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
-    const double v = sum_strided(part + (int64_t)s0 * dk + r0 * k + e, dk, s1 - s0);
-    Yi[(int64_t)b * dk + r0 * k + e] = v;
-    ys[e] = v;
+  constexpr int EPT = kGramRows * KM / kBlock;
+  double acc[EPT];
+  sum_rows<EPT>(part + (int64_t)s0 * dk + r0 * k, dk, s1 - s0, rows * k, acc);
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    if (e < rows * k) {
+      Yi[(int64_t)b * dk + r0 * k + e] = acc[u];
+      ys[e] = acc[u];
+    }
   }
   __syncthreads();
   gram_tile<kc_of(KM)>(ys, ys, rows, k, gram + ((int64_t)b * nch + c) * k * k);
@@ -357,10 +393,17 @@ aggregate_gram_kernel(int m, int64_t d, int k, const double* __restrict__ Yi, do
   const int64_t r0 = (int64_t)c * kGramRows;
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const int64_t dk = d * k;
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
-    const double v = scale * sum_strided(Yi + r0 * k + e, dk, m);
-    Y[r0 * k + e] = v;
-    ys[e] = v;
+  constexpr int EPT = kGramRows * KM / kBlock;
+  double acc[EPT];
+  sum_rows<EPT>(Yi + r0 * k, dk, m, rows * k, acc);
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    if (e < rows * k) {
+      const double v = scale * acc[u];
+      Y[r0 * k + e] = v;
+      ys[e] = v;
+    }
   }
   __syncthreads();
   gram_tile<kc_of(KM)>(ys, ys, rows, k, gram + (int64_t)c * k * k);
