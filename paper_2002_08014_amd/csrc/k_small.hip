@@ -112,30 +112,37 @@ __device__ inline double sum_strided(const T* __restrict__ p, int64_t stride, in
 
 // acc[u] = sum over q < n of p[q * stride + e_u] for this thread's elements
 // e_u = threadIdx.x + u * kBlock (0 where e_u >= count), added in increasing q.
-// The loads of two steps for all EPT elements are issued together, so a
-// thread has 2 EPT loads in flight instead of one element's at a time.
+// The loads of QU consecutive q for all EPT elements (32 in all) are issued
+// together, instead of one element's at a time.
 template <int EPT, typename T>
 __device__ inline void sum_rows(const T* __restrict__ p, int64_t stride, int n, int count,
                                 double (&acc)[EPT]) {
+  constexpr int QU = EPT >= 16 ? 2 : 32 / EPT;
 #pragma unroll
   for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
   int q = 0;
-  for (; q + 1 < n; q += 2) {
-    double v0[EPT], v1[EPT];
+  for (; q + QU <= n; q += QU) {
+    double v[QU][EPT];
+    // unconditional loads (clamped index, then zeroed): a load under a branch is
+    // waited for inside its branch, which would serialise all of them
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      v0[u] = e < count ? (double)p[(int64_t)q * stride + e] : 0.0;
-      v1[u] = e < count ? (double)p[(int64_t)(q + 1) * stride + e] : 0.0;
-    }
+    for (int j = 0; j < QU; ++j)
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) acc[u] = (acc[u] + v0[u]) + v1[u];
+      for (int u = 0; u < EPT; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        v[j][u] = (double)p[(int64_t)(q + j) * stride + min(e, count - 1)];
+      }
+#pragma unroll
+    for (int j = 0; j < QU; ++j)
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) acc[u] += (threadIdx.x + u * kBlock < count) ? v[j][u] : 0.0;
   }
-  if (q < n) {
+  for (; q < n; ++q) {
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = threadIdx.x + u * kBlock;
-      acc[u] += e < count ? (double)p[(int64_t)q * stride + e] : 0.0;
+      const double x = (double)p[(int64_t)q * stride + min(e, count - 1)];
+      acc[u] += e < count ? x : 0.0;
     }
   }
 }
