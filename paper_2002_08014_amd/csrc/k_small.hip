@@ -71,6 +71,21 @@ __device__ void gram_tile(const double* Xs, const double* Ws, int rows, int k, d
 // 16-column blocks needed for k columns
 constexpr int kc_of(int km) { return (km + 15) / 16; }
 
+// dst[e] = src[e] for e < count (global -> LDS), at most EPT elements per
+// thread.  All loads are issued (clamped index) before the first store: a store
+// right after each load waits for it, one round trip per element.
+template <int EPT>
+__device__ inline void load_tile(const double* __restrict__ src, int count, double* dst) {
+  double v[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) v[u] = src[min((int)threadIdx.x + u * kBlock, count - 1)];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    if (e < count) dst[e] = v[u];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // G_b(chunk) = X_b[rows]^T W_b[rows]  (k x k partial, chunk of kGramRows rows)
 // grid: (nchunks, batch), block kBlock
@@ -88,10 +103,8 @@ cross_gram_kernel(int64_t d, int k, const double* __restrict__ X, int64_t x_stri
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const double* Xb = X + b * x_stride + r0 * k;
   const double* Wb = W + b * w_stride + r0 * k;
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) {
-    xs[e] = Xb[e];
-    ws[e] = Wb[e];
-  }
+  load_tile<4 * KC>(Xb, rows * k, xs);
+  load_tile<4 * KC>(Wb, rows * k, ws);
   __syncthreads();
   gram_tile<KC>(xs, ws, rows, k, out + ((int64_t)b * nchunks + c) * k * k);
 }
@@ -471,7 +484,7 @@ apply_gram_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
   const int64_t r0 = (int64_t)c * kGramRows;
   const int rows = (int)min<int64_t>(kGramRows, d - r0);
   const int64_t base = (int64_t)b * d * k + r0 * k;
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = X[base + e];
+  load_tile<4 * KC>(X + base, rows * k, Xs);
   if constexpr (FACTOR) {
     static_assert(KC == 1, "in-kernel factorization only for k <= 16");
     __shared__ double G[KM * KM];
@@ -482,7 +495,7 @@ apply_gram_kernel(int64_t d, int k, int nch_in, const double* __restrict__ X,
     chol_inv_wave<KM>(G, Ri, k, &bad);
     if (threadIdx.x == 0 && c == 0 && bad && flags != nullptr) flags[b] = 1;
   } else {
-    for (int e = threadIdx.x; e < k * k; e += kBlock) Ri[e] = rin[(int64_t)b * k * k + e];
+    load_tile<KC * KC>(rin + (int64_t)b * k * k, k * k, Ri);
     __syncthreads();
   }
   double res[KC][4];
@@ -573,8 +586,8 @@ right_mult_kernel(int64_t d, int k, const double* __restrict__ X, const double* 
   const int rows = (int)min<int64_t>(TR, d - r0);
   const double* Sb = S + b * s_stride;
   const double* Xb = X + (int64_t)b * d * k + r0 * k;
-  for (int e = threadIdx.x; e < k * k; e += kBlock) Ss[e] = Sb[e];
-  for (int e = threadIdx.x; e < rows * k; e += kBlock) Xs[e] = Xb[e];
+  load_tile<KC * KC>(Sb, k * k, Ss);
+  load_tile<4 * KC>(Xb, rows * k, Xs);
   __syncthreads();
   double res[KC][4];
   tile_times_s<KC>(Xs, Ss, rows, k, upper != 0, res);
