@@ -1,14 +1,14 @@
 // Two-pass local multiply on FP32 matrix cores, for the shapes the fused
 // kernels do not cover (large d, k up to 64, FP32 or BF16 A):
 //   pass 1  t = A_rows Z_i              (per 128-row block of a work item)
-//   pass 2  part = A_rows^T t           (per 128-column block of a work item)
+//   pass 2  part = A_rows^T t           (per 256-column block of a work item)
 // (Eq. (power_yi) without 1/s_i; the per-item partials are reduced per
 // partition in FP64 afterwards.)  A is read twice; at k = 64 the two products
 // cost 4 n d k flops against 2 n d b bytes, so FP32 matrix-core throughput,
 // not HBM, bounds this path.
 //
-// Both kernels: 256 threads (4 waves), a 128 x (16 NT) output block per
-// workgroup, K staged through LDS 16 at a time in two buffers (the next slice
+// Both kernels: 256 threads (4 waves), a 128 (pass 1) or 256 (pass 2) x (16 NT)
+// output block per workgroup, K staged through LDS 16 at a time in two buffers (the next slice
 // is fetched into registers while the current one is multiplied), operands
 // read from LDS one element per lane in the v_mfma_f32_16x16x4f32 layouts
 // (A: lane l holds [l%16][l/16]; B: [l/16][l%16]; D: rows 4(l/16)+r, col l%16).
@@ -20,7 +20,11 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 128;   // output rows (pass 1) or columns (pass 2) per workgroup
+// output rows per workgroup of pass 1 and output columns per workgroup of pass 2
+// (4 waves x 16-row or 16-column blocks; measured best at k = 64: 98 and 109
+// TFLOP/s, against 95 with 256 rows in pass 1 and 104 with 128 columns in pass 2)
+constexpr int kBM1 = 128;
+constexpr int kBM2 = 256;
 constexpr int kBK = 16;    // contraction slice staged per step (16 measured 11-12 % faster
                            // than 32 at k = 64: half the LDS, five waves per SIMD instead of two)
 
@@ -47,27 +51,28 @@ __device__ inline f4 load4<__hip_bfloat16>(const __hip_bfloat16* p) {
 
 // pass 1: t[row][n] = sum_c A[row][c] Z[c][n]; grid (items, ceil(max item rows / 128));
 // BK: contraction slice staged per step
-template <typename TA, int NT, int BK>
+template <typename TA, int NT, int BK, int MT>
 __global__ void __launch_bounds__(256)
 tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ Zw,
            int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ t) {
   constexpr int N = 16 * NT;
+  constexpr int BM = 64 * MT;            // rows per workgroup (4 waves x MT 16-row blocks)
   constexpr int AP = BK + 4;             // padded A row (floats)
   constexpr int ZP = pad16(N);           // padded Z row
   constexpr int ZE = (BK * N) / 256;     // Z elements per thread per slice
   constexpr int AQ = BK / 4;             // 4-element groups per A row
-  constexpr int AE = (kBM * AQ) / 256;   // 4-element groups per thread per slice
-  __shared__ float As[2][kBM * AP];
+  constexpr int AE = (BM * AQ) / 256;    // 4-element groups per thread per slice
+  __shared__ float As[2][BM * AP];
   __shared__ float Zs[2][BK * ZP];
   const WorkItem it = items[blockIdx.x];
-  const int64_t r0 = (int64_t)blockIdx.y * kBM;
+  const int64_t r0 = (int64_t)blockIdx.y * BM;
   if (r0 >= it.rows) return;
-  const int rows = (int)min<int64_t>(kBM, it.rows - r0);
+  const int rows = (int)min<int64_t>(BM, it.rows - r0);
   const TA* Ab = A + (it.row0 + r0) * lda;
   const float* Z = Zw + (int64_t)it.part * z_stride;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, i = lane & 15;
 
-  // staging: A slice 128 x BK as AE groups of 4 elements per thread (row (tid + 256 j) / AQ,
+  // staging: A slice BM x BK as AE groups of 4 elements per thread (row (tid + 256 j) / AQ,
   // cols 4 (tid % AQ)..)
   f4 pa[AE];
   float pz[ZE];
@@ -96,9 +101,9 @@ tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
     }
   };
 
-  f4 acc[2][NT];
+  f4 acc[MT][NT];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
 
@@ -111,13 +116,13 @@ tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
     if (s + 1 < nsl) fetch((int64_t)(s + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      float a[2], z[NT];
+      float a[MT], z[NT];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) a[mt] = As[b][(32 * w + 16 * mt + i) * AP + 4 * kk + g];
+      for (int mt = 0; mt < MT; ++mt) a[mt] = As[b][(16 * MT * w + 16 * mt + i) * AP + 4 * kk + g];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) z[nt] = Zs[b][(4 * kk + g) * ZP + 16 * nt + i];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], z[nt], acc[mt][nt], 0, 0, 0);
@@ -127,45 +132,47 @@ tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
   }
   float* tb = t + (it.row0 + r0) * k;
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 32 * w + 16 * mt + 4 * g + r;
+        const int row = 16 * MT * w + 16 * mt + 4 * g + r;
         const int n = 16 * nt + i;
         if (row < rows && n < k) tb[(int64_t)row * k + n] = acc[mt][nt][r];
       }
 }
 
 // pass 2: part[slot][c][n] = sum_{rows of item} A[row][c] t[row][n]; grid (items, ceil(d / 128))
-template <typename TA, int NT, int BK>
+template <typename TA, int NT, int BK, int MT>
 __global__ void __launch_bounds__(256)
 ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ t,
            const WorkItem* __restrict__ items, float* __restrict__ part) {
   constexpr int N = 16 * NT;
-  constexpr int AP = kBM + 16;           // padded A slice row (floats)
+  constexpr int BM = 64 * MT;            // columns per workgroup (4 waves x MT 16-column blocks)
+  constexpr int AP = BM + 16;            // padded A slice row (floats)
+  constexpr int AQ = BM / 4;             // 4-element groups per A slice row
   constexpr int TP = pad16(N);
   constexpr int TE = (BK * N) / 256;
-  constexpr int AE = BK / 8;             // 4-element groups per thread per slice
+  constexpr int AE = (BK * AQ) / 256;    // 4-element groups per thread per slice
   __shared__ float As[2][BK * AP];
   __shared__ float Ts[2][BK * TP];
   const WorkItem it = items[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * kBM;
+  const int64_t c0 = (int64_t)blockIdx.y * BM;
   const int rows = (int)it.rows;
   const TA* Ab = A + it.row0 * lda + c0;
   const float* tb = t + it.row0 * k;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, i = lane & 15;
 
-  // staging: A slice BK rows x 128 columns, thread -> row tid/32 + 8j, cols 4(tid%32)..
+  // staging: A slice BK rows x BM columns, thread -> row (tid + 256 j) / AQ, cols 4 (tid % AQ)..
   f4 pa[AE];
   float pt[TE];
   auto fetch = [&](int rs) {
 #pragma unroll
     for (int j = 0; j < AE; ++j) {
-      const int r = rs + tid / 32 + 8 * j;
-      const int64_t c = c0 + 4 * (tid % 32);
-      pa[j] = (r < rows && c < d) ? load4<TA>(Ab + (int64_t)r * lda + 4 * (tid % 32))
+      const int r = rs + (tid + 256 * j) / AQ;
+      const int64_t c = c0 + 4 * (tid % AQ);
+      pa[j] = (r < rows && c < d) ? load4<TA>(Ab + (int64_t)r * lda + 4 * (tid % AQ))
                                   : f4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
@@ -177,7 +184,7 @@ ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
   };
   auto stash = [&](int b) {
 #pragma unroll
-    for (int j = 0; j < AE; ++j) *(f4*)&As[b][(tid / 32 + 8 * j) * AP + 4 * (tid % 32)] = pa[j];
+    for (int j = 0; j < AE; ++j) *(f4*)&As[b][((tid + 256 * j) / AQ) * AP + 4 * (tid % AQ)] = pa[j];
 #pragma unroll
     for (int j = 0; j < TE; ++j) {
       const int e = tid + 256 * j;
@@ -185,9 +192,9 @@ ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
     }
   };
 
-  f4 acc[2][NT];
+  f4 acc[MT][NT];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
 
@@ -200,13 +207,13 @@ ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
     if (s + 1 < nsl) fetch((s + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      float a[2], y[NT];
+      float a[MT], y[NT];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) a[mt] = As[b][(4 * kk + g) * AP + 32 * w + 16 * mt + i];
+      for (int mt = 0; mt < MT; ++mt) a[mt] = As[b][(4 * kk + g) * AP + 16 * MT * w + 16 * mt + i];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) y[nt] = Ts[b][(4 * kk + g) * TP + 16 * nt + i];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], y[nt], acc[mt][nt], 0, 0, 0);
@@ -216,12 +223,12 @@ ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
   }
   float* o = part + (int64_t)it.slot * d * k;
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t c = c0 + 32 * w + 16 * mt + 4 * g + r;
+        const int64_t c = c0 + 16 * MT * w + 16 * mt + 4 * g + r;
         const int n = 16 * nt + i;
         if (c < d && n < k) o[c * k + n] = acc[mt][nt][r];
       }
@@ -231,13 +238,13 @@ template <typename TA, int NT>
 hipError_t gemm_pair(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
                      int64_t z_stride, void* tbuf, void* part, const WorkItem* items, int nitems,
                      hipStream_t s) {
-  dim3 g1(nitems, (unsigned)((P.chunk_rows + kBM - 1) / kBM));
-  tmm_kernel<TA, NT, kBK><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)Zw, z_stride, items,
+  dim3 g1(nitems, (unsigned)((P.chunk_rows + kBM1 - 1) / kBM1));
+  tmm_kernel<TA, NT, kBK, kBM1 / 64><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)Zw, z_stride, items,
                                         (float*)tbuf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 g2(nitems, (unsigned)((P.d + kBM - 1) / kBM));
-  ymm_kernel<TA, NT, kBK><<<g2, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)tbuf, items,
+  dim3 g2(nitems, (unsigned)((P.d + kBM2 - 1) / kBM2));
+  ymm_kernel<TA, NT, kBK, kBM2 / 64><<<g2, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)tbuf, items,
                                         (float*)part);
   return hipGetLastError();
 }
