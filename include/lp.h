@@ -161,6 +161,11 @@ typedef struct {
                             so each half still fills the GPU; the fused kernels run one
                             workgroup per item, and half the items leave half the chip
                             idle) */
+  int32_t k_ref;         /* columns of U_ref: 0 (default) means k; else 1 <= k_ref <= k, so
+                            the run iterates at rank k (the iteration rank r of Algorithm 1,
+                            r >= target rank) and sin_hist records sin theta_{k_ref}(Z_r,
+                            U_ref) = ||(I - Z_r Z_r^T) U_ref|| with Z_r of k columns (the
+                            distance of the appendix on the eigengap, Theorem there) */
 } lp_run_opts;
 
 typedef struct {
@@ -179,7 +184,10 @@ typedef struct {
 } lp_run_stats;
 
 /* Run LocalPower (Algorithm 1) for T communication rounds.
- *   k       : target = iteration rank, 1 <= k <= k_max, k <= every s_i.
+ *   k       : iteration rank r of Algorithm 1, 1 <= k <= k_max, k <= every s_i.  With a
+ *             target rank below it (oversampling), pass the target as opts->k_ref and
+ *             ritz_out: the first k_ref columns of Z_out (Ritz vectors, descending) and
+ *             of ritz_out are the target-rank results.
  *   p_sched : host int32[T], p_sched[r] >= 1 local iterations in round r (fixed p,
  *             a decaying schedule, or p = T total for one-shot); COPIED.
  *   mode    : alignment used when p_sched[r] >= 2 (rounds with p = 1 use none).
@@ -239,6 +247,14 @@ lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters,
  * (no workspace), synchronises and writes the result to *out_host. */
 lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
                        void* stream);
+
+/* sin theta_k(Z, U) = ||(I - Z Z^T) U||_2 for a device d x r FP64 iterate Z with
+ * orthonormal columns and a device d x k FP64 reference U, 1 <= k <= r <= min(d, 64)
+ * (Definition 1 with the iteration rank above the target rank, as in the appendix on
+ * the eigengap).  Same scratch, synchronisation and result as lp_sin_theta, which is
+ * the case r = k. */
+lp_status lp_sin_theta_r(const double* Z, int32_t r, const double* U, int32_t k, int64_t d,
+                         double* out_host, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Serving: many LocalPower jobs on one GPU.  (Runtime around the method, not

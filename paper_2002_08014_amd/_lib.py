@@ -24,7 +24,7 @@ MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_local_multiply", "lp_orth", "lp_align",
-           "lp_sin_theta", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
+           "lp_sin_theta", "lp_sin_theta_r", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
            "lp_server_destroy")
 
@@ -51,7 +51,8 @@ class RunOpts(ctypes.Structure):
                 ("z0_orthonormal", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32),
                 ("time_local", ctypes.c_int32),
-                ("split_rounds", ctypes.c_int32)]
+                ("split_rounds", ctypes.c_int32),
+                ("k_ref", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -140,6 +141,8 @@ def load() -> ctypes.CDLL:
     L.lp_copy_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_sin_theta.restype = i32
     L.lp_sin_theta.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.lp_sin_theta_r.restype = i32
+    L.lp_sin_theta_r.argtypes = [vp, i32, vp, i32, i64, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_server_footprint.restype = i32
     L.lp_server_footprint.argtypes = [ctypes.POINTER(Job), ctypes.POINTER(sz)]
     L.lp_server_create.restype = i32
@@ -276,7 +279,9 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
     """Returns dict(Z, ritz, sin_hist, signs, stats); Z is a device d x k float64 tensor.
     time_local: 0 no events, 1 (or True) every local multiply timed, 2 the first
     one of every round only.  split_rounds: partitions in two halves on two streams
-    (None: the library decides, True: always, False: never)."""
+    (None: the library decides, True: always, False: never).  k is the iteration
+    rank; U_ref may have fewer columns (the target rank), and sin_hist then holds
+    sin theta of the rank-k iterate against it."""
     L = load()
     dev = P.A.device
     sched = np.ascontiguousarray(np.asarray(p_sched, dtype=np.int32))
@@ -294,7 +299,10 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
     if U_ref is not None:
         Ud = _dev_f64(U_ref, dev)
         hist = np.zeros(T, dtype=np.float64)
+        if Ud.dim() != 2 or Ud.shape[0] != P.d or not 1 <= Ud.shape[1] <= k:
+            raise ValueError("U_ref must be d x k_ref with 1 <= k_ref <= k")
         opts.U_ref = Ud.data_ptr()
+        opts.k_ref = Ud.shape[1]
         opts.sin_hist = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     signs = None
     if record_signs:
@@ -344,11 +352,18 @@ def lp_align(P: Problem, mode: str, Zi: torch.Tensor, Zb: torch.Tensor) -> torch
 
 
 def lp_sin_theta(Z: torch.Tensor, U: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> float:
+    """sin theta of a d x r iterate Z against a d x k reference U (k <= r); Definition 1."""
     L = load()
     Zd, Ud = Z.contiguous(), U.contiguous()
     out = ctypes.c_double(0.0)
-    _check(L.lp_sin_theta(_ptr(Zd), _ptr(Ud), Zd.shape[0], Zd.shape[1], ctypes.byref(out),
-                          _stream_handle(stream)), "lp_sin_theta")
+    if Zd.shape[1] == Ud.shape[1]:
+        _check(L.lp_sin_theta(_ptr(Zd), _ptr(Ud), Zd.shape[0], Zd.shape[1], ctypes.byref(out),
+                              _stream_handle(stream)), "lp_sin_theta")
+    else:
+        if Zd.shape[0] != Ud.shape[0]:
+            raise ValueError("Z and U need the same row count")
+        _check(L.lp_sin_theta_r(_ptr(Zd), Zd.shape[1], _ptr(Ud), Ud.shape[1], Zd.shape[0],
+                                ctypes.byref(out), _stream_handle(stream)), "lp_sin_theta_r")
     return float(out.value)
 
 

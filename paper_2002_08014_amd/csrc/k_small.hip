@@ -870,22 +870,24 @@ sym_eig_kernel(int nchunks, int k, const double* __restrict__ part, double* __re
 }
 
 // ---------------------------------------------------------------------------
-// sin theta_k(Z, U) = sqrt(lambda_max(W^T W)), W = U - Z (Z^T U); one workgroup
+// sin theta_k(Z, U) = sqrt(lambda_max(W^T W)), W = U - Z (Z^T U); one workgroup.
+// Z is d x r (the iterate, r >= k columns), U is d x k (the reference).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
-sin_theta_kernel(int64_t d, int k, const double* __restrict__ Z, const double* __restrict__ U,
-                 double* __restrict__ out, double* __restrict__ hist, int32_t* __restrict__ ctr) {
+sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
+                 const double* __restrict__ U, double* __restrict__ out,
+                 double* __restrict__ hist, int32_t* __restrict__ ctr) {
   __shared__ double C[kMaxK * kMaxK];
   __shared__ double G[kMaxK * kMaxK];
   __shared__ double Wt[16 * kMaxK];
   __shared__ double cs[kMaxK / 2 + 1], sn[kMaxK / 2 + 1];
   __shared__ int flag;
   const int kk = k * k;
-  // C = Z^T U
-  for (int e = threadIdx.x; e < kk; e += blockDim.x) {
+  // C = Z^T U (r x k)
+  for (int e = threadIdx.x; e < r * k; e += blockDim.x) {
     const int i = e / k, j = e - (e / k) * k;
     double s = 0.0;
-    for (int64_t r = 0; r < d; ++r) s = fma(Z[r * k + i], U[r * k + j], s);
+    for (int64_t q = 0; q < d; ++q) s = fma(Z[q * r + i], U[q * k + j], s);
     C[e] = s;
   }
   double g[(kMaxK * kMaxK) / kBlock];
@@ -896,9 +898,9 @@ sin_theta_kernel(int64_t d, int k, const double* __restrict__ Z, const double* _
     const int rows = (int)min<int64_t>(16, d - r0);
     for (int e = threadIdx.x; e < rows * k; e += blockDim.x) {
       const int rr = e / k, j = e - (e / k) * k;
-      const double* zr = Z + (r0 + rr) * k;
+      const double* zr = Z + (r0 + rr) * r;
       double s = U[(r0 + rr) * k + j];
-      for (int l = 0; l < k; ++l) s = fma(-zr[l], C[l * k + j], s);
+      for (int l = 0; l < r; ++l) s = fma(-zr[l], C[l * k + j], s);
       Wt[e] = s;
     }
     __syncthreads();
@@ -1034,9 +1036,9 @@ hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* l
   return hipGetLastError();
 }
 
-hipError_t launch_sin_theta(int64_t d, int k, const double* Z, const double* U, double* out,
-                            double* hist, int32_t* ctr, hipStream_t s) {
-  sin_theta_kernel<<<1, kBlock, 0, s>>>(d, k, Z, U, out, hist, ctr);
+hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const double* U,
+                            double* out, double* hist, int32_t* ctr, hipStream_t s) {
+  sin_theta_kernel<<<1, kBlock, 0, s>>>(d, r, k, Z, U, out, hist, ctr);
   return hipGetLastError();
 }
 

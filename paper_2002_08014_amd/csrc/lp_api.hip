@@ -314,7 +314,7 @@ hipError_t timing_pair(lp_problem* P, hipEvent_t* ev0, hipEvent_t* ev1) {
 // the base's last local orthonormalisation.  The two halves join before the
 // aggregation.  When the step is timed, one pair of events brackets both
 // halves' local multiplies (back to back in the chain).
-hipError_t enqueue_round_split(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
+hipError_t enqueue_round_split(lp_problem* P, int k, int p, lp_agg mode, int hist) {
   Ptrs q = ptrs(P);
   const int64_t d = P->d;
   const int64_t dk = d * k;
@@ -371,14 +371,14 @@ hipError_t enqueue_round_split(lp_problem* P, int k, int p, lp_agg mode, bool hi
   const hipStream_t s = st[0];
   LP_TRY(launch_aggregate_gram(P->m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, q.gram, s));
   LP_TRY(cholqr2_from_gram(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + P->m, s));
-  if (hist) LP_TRY(launch_sin_theta(d, k, q.Z, q.Uref, nullptr, q.hist, q.ctr, s));
+  if (hist > 0) LP_TRY(launch_sin_theta(d, k, hist, q.Z, q.Uref, nullptr, q.hist, q.ctr, s));
 #undef LP_TRY
   return hipSuccess;
 }
 
 // Enqueue one communication round with p local steps (only kernel launches, so
 // the sequence can be captured into a graph).
-hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
+hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, int hist) {
   if (P->split_now) return enqueue_round_split(P, k, p, mode, hist);
   Ptrs q = ptrs(P);
   hipStream_t s = P->stream;
@@ -422,19 +422,21 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, bool hist) {
   if ((e = cholqr2_from_gram(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + m, s)) !=
       hipSuccess)
     return e;
-  if (hist) {
-    if ((e = launch_sin_theta(d, k, q.Z, q.Uref, nullptr, q.hist, q.ctr, s)) != hipSuccess) return e;
+  if (hist > 0) {
+    if ((e = launch_sin_theta(d, k, hist, q.Z, q.Uref, nullptr, q.hist, q.ctr, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, bool hist, bool use_graph,
+// hist > 0: after the round, append sin theta of Z (d x k) against the first
+// hist columns of the reference to the device history.
+lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, int hist, bool use_graph,
                     int slot) {
   if (!use_graph) {
     LP_HIP(enqueue_round(P, k, p, mode, hist));
     return LP_OK;
   }
-  GraphKey key{k, p, (int)mode, hist ? 1 : 0, slot, slot >= 0 && P->timing_first_only ? 1 : 0,
+  GraphKey key{k, p, (int)mode, hist, slot, slot >= 0 && P->timing_first_only ? 1 : 0,
                P->split_now ? 1 : 0};
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
@@ -574,7 +576,7 @@ lp_status drive_begin(lp_problem* P, int k, const double* Y0, bool orthonormal) 
 lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode) {
   if (p < 1) return fail(LP_EINVAL, "p must be >= 1");
   P->split_now = false;   // served jobs keep to their own stream
-  return run_round(P, k, p, mode, false, true, -1);
+  return run_round(P, k, p, mode, 0, true, -1);
 }
 
 const double* drive_z(lp_problem* P) { return ptrs(P).Z; }
@@ -903,6 +905,9 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     if (n < offsetof(lp_run_opts, use_graph) + sizeof(int32_t)) o.use_graph = 1;
   }
   const bool hist = o.U_ref != nullptr && o.sin_hist != nullptr;
+  if (o.k_ref < 0 || o.k_ref > k) return fail(LP_EINVAL, "k_ref must be 0 or in [1, k]");
+  const int k_ref = o.k_ref > 0 ? o.k_ref : k;
+  const int hist_k = hist ? k_ref : 0;
   if (o.time_local < 0 || o.time_local > 2) return fail(LP_EINVAL, "time_local must be 0, 1 or 2");
   if (o.split_rounds < 0 || o.split_rounds > 2) return fail(LP_EINVAL, "split_rounds must be 0, 1 or 2");
   bool split;
@@ -938,7 +943,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   if ((st = join_in(P)) != LP_OK) return st;
   LP_HIP(launch_fill_i32(q.flags, m + 2, 0, s));
   LP_HIP(launch_fill_i32(q.ctr, 1, 0, s));
-  if (hist) LP_HIP(hipMemcpyAsync(q.Uref, o.U_ref, dk * 8, hipMemcpyDeviceToDevice, s));
+  if (hist) LP_HIP(hipMemcpyAsync(q.Uref, o.U_ref, (size_t)d * k_ref * 8, hipMemcpyDeviceToDevice, s));
   // Z_0 = orth(Y_0) (Algorithm 1, initialisation)
   if (o.z0_orthonormal) {
     LP_HIP(hipMemcpyAsync(q.Z, Y0, dk * 8, hipMemcpyDeviceToDevice, s));
@@ -959,19 +964,19 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     if (!timed_graph && timing && !pending.empty()) LP_HIP(harvest_slots(P, pending));
     if (timed_graph) {
       const int slot = (int)pending.size();
-      st = run_round(P, k, p, mode, hist, true, slot);
+      st = run_round(P, k, p, mode, hist_k, true, slot);
       if (st != LP_OK) {
         // the runtime refused the captured event records: time with plain launches
         // (the refusal stays readable through lp_last_error)
         P->timed_graphs_ok = false;
         LP_HIP(harvest_slots(P, pending));
-        st = run_round(P, k, p, mode, hist, false, -1);
+        st = run_round(P, k, p, mode, hist_k, false, -1);
       } else {
         pending.emplace_back(slot, P->timing_first_only ? 1 : p);
         graph_rounds++;
       }
     } else {
-      st = run_round(P, k, p, mode, hist, graph && !timing, -1);
+      st = run_round(P, k, p, mode, hist_k, graph && !timing, -1);
       if (graph && !timing) graph_rounds++;
     }
     if (st != LP_OK) {
@@ -1142,12 +1147,18 @@ lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters,
 
 lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
                        void* stream) {
+  return lp_sin_theta_r(Z, k, U, k, d, out_host, stream);
+}
+
+lp_status lp_sin_theta_r(const double* Z, int32_t r, const double* U, int32_t k, int64_t d,
+                         double* out_host, void* stream) {
   if (Z == nullptr || U == nullptr || out_host == nullptr) return fail(LP_EINVAL, "NULL argument");
-  if (d < 1 || k < 1 || k > kMaxK || k > d) return fail(LP_EINVAL, "need 1 <= k <= min(d, 64)");
+  if (d < 1 || k < 1 || r < k || r > kMaxK || r > d)
+    return fail(LP_EINVAL, "need 1 <= k <= r <= min(d, 64)");
   hipStream_t s = (hipStream_t)stream;
   double* slot = nullptr;
   LP_HIP(sin_slot_address(&slot));
-  LP_HIP(launch_sin_theta(d, k, Z, U, slot, nullptr, nullptr, s));
+  LP_HIP(launch_sin_theta(d, r, k, Z, U, slot, nullptr, nullptr, s));
   LP_HIP(hipMemcpyAsync(out_host, slot, sizeof(double), hipMemcpyDeviceToHost, s));
   LP_HIP(hipStreamSynchronize(s));
   return LP_OK;

@@ -223,10 +223,11 @@ hipError_t launch_aggregate(int m, int64_t d, int k, const double* Yi, double sc
 hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* lam, double* V,
                           hipStream_t s);
 
-// sin theta_k in one workgroup (no scratch): writes out[0] (device) and, if
-// hist != NULL, hist[*ctr] then increments *ctr.
-hipError_t launch_sin_theta(int64_t d, int k, const double* Z, const double* U, double* out,
-                            double* hist, int32_t* ctr, hipStream_t s);
+// sin theta_k(Z, U) of a d x r iterate Z against a d x k reference U (r >= k) in
+// one workgroup (no scratch): writes out[0] (device) and, if hist != NULL,
+// hist[*ctr] then increments *ctr.
+hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const double* U,
+                            double* out, double* hist, int32_t* ctr, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
 

@@ -145,7 +145,7 @@ lp_status launch(lp_server* S, Job* j) {
   const int64_t dk = j->spec.d * j->spec.k;
   lp_status st = lp::drive_round(P, j->spec.k, j->p, j->spec.mode);
   if (st != LP_OK) return st;
-  if (lp::launch_sin_theta(j->spec.d, j->spec.k, lp::drive_z(P), j->zprev, j->change_dev, nullptr,
+  if (lp::launch_sin_theta(j->spec.d, j->spec.k, j->spec.k, lp::drive_z(P), j->zprev, j->change_dev, nullptr,
                            nullptr, s) != hipSuccess ||
       hipMemcpyAsync(j->zprev, lp::drive_z(P), dk * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(S->pinned + j->slot, j->change_dev, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||

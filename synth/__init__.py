@@ -12,6 +12,7 @@ from .workloads import (  # noqa: F401
     haar,
     spectrum_c1,
     spectrum_gap,
+    spectrum_cluster,
     power_law_cov,
     lowrank_plus_noise,
     gaussian_rows,

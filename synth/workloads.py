@@ -311,3 +311,19 @@ def make_small(n: int, d: int, k: int, m: int, seed: int = 0, dtype=torch.float6
     return Workload(f"small-{n}x{d}-k{k}-m{m}", A, offs, k,
                     p_sched if p_sched is not None else fixed_schedule(4, 10), mode,
                     gaussian_start(d, k, seed), sig, seed)
+
+
+def spectrum_cluster(d: int, k: int, r: int, spread: float = 0.985, drop: float = 0.45,
+                     decay: float = 0.8) -> np.ndarray:
+    """A small gap after the target rank and a large one after the iteration rank:
+    sigma_j = 1/j for j <= k, sigma_{j+1} = spread * sigma_j for k <= j < r,
+    sigma_{r+1} = drop * sigma_r, then geometric decay."""
+    s = np.empty(d, dtype=np.float64)
+    s[:k] = 1.0 / np.arange(1, k + 1, dtype=np.float64)
+    for j in range(k, min(r, d)):
+        s[j] = s[j - 1] * spread
+    if d > r:
+        s[r] = s[r - 1] * drop
+        for j in range(r + 1, d):
+            s[j] = s[j - 1] * decay
+    return s

@@ -256,6 +256,9 @@ def test_invalid_arguments(lib, fp64_small):
         lib.lp_run(P2, 5, [1], "sign", w.Y0)                 # s_0 = 3 < k
     with pytest.raises(lib.LPError):
         lib.lp_create(to_device(w), [0, 3, 3, 2000], 5)      # empty partition
+    Zt = torch.zeros(100, 4, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(lib.LPError):
+        lib.lp_sin_theta(Zt, torch.zeros(100, 5, dtype=torch.float64, device="cuda:0"))  # k > r
 
 
 def test_create_right_after_queued_work(lib):
@@ -347,3 +350,51 @@ def test_split_rounds_base_in_second_half(lib):
         assert torch.equal(r1["Z"], r2["Z"])
         ro = oracle.localpower(w.A.numpy(), offsets, k, w.p_sched, mode, w.Y0)
         assert sin_theta_np(host(r2["Z"]), ro["Z"]) < 1e-10
+
+
+# --------------------------------------------------------------------- iteration rank r > k
+
+@pytest.mark.parametrize("mode,p", [("sign", 4), ("opt", 4), ("sign", 1)])
+def test_oversampled_run(lib, mode, p):
+    """Iteration rank r = 8 above the target rank k = 4 (Algorithm 1's r >= k):
+    sin theta_k of the rank-r iterate per round, Z and the top-k Ritz pairs
+    against the oracle.  The data put sigma_k close to sigma_{k+1} and a wide gap
+    after sigma_r."""
+    n, d, k, r, m = 2400, 60, 4, 8, 4
+    _flush(f"oversampled {mode} p={p}")
+    sig = synth.spectrum_cluster(d, k, r)
+    A = synth.lowrank_plus_noise(n, d, sig, 0.0, 5)
+    offs = synth.equal_offsets(n, m)
+    Y0 = synth.gaussian_start(d, r, 5)
+    U, _ = oracle.top_k(A.numpy(), k)
+    P = _problem(lib, A.to("cuda:0"), offs, r)
+    sched = [p] * 12
+    g = lib.lp_run(P, r, sched, mode, Y0, ritz=True, U_ref=torch.as_tensor(U))
+    ro = oracle.localpower(A.numpy(), offs, r, sched, mode, Y0, U_ref=U)
+    assert ro["ambiguous"] == 0
+    assert np.abs(g["sin_hist"] - np.array(ro["sin_hist"])).max() < 1e-10
+    lam_o, Zr_o, _ = oracle.ritz(A.numpy(), ro["Z"])
+    assert np.abs(host(g["ritz"]) - lam_o).max() < 1e-10 * lam_o[0]
+    Zg = host(g["Z"])
+    assert sin_theta_np(Zg[:, :k], Zr_o[:, :k]) < 1e-9
+    assert abs(lib.lp_sin_theta(g["Z"], torch.as_tensor(U, device="cuda:0"))
+               - oracle.sin_theta(Zr_o, U)) < 1e-10
+    # the same problem and rank with the full-width reference (another history width)
+    U8, _ = oracle.top_k(A.numpy(), r)
+    g8 = lib.lp_run(P, r, sched, mode, Y0, U_ref=torch.as_tensor(U8))
+    ro8 = oracle.localpower(A.numpy(), offs, r, sched, mode, Y0, U_ref=U8)
+    assert np.abs(g8["sin_hist"] - np.array(ro8["sin_hist"])).max() < 1e-10
+    with pytest.raises(ValueError):
+        lib.lp_run(P, k, sched, mode, Y0[:, :k], U_ref=torch.as_tensor(U8))   # k_ref > k
+
+
+def test_sin_theta_wider_iterate(lib):
+    _flush("sin theta, r > k")
+    rng = np.random.default_rng(3)
+    for d, r, k in ((100, 8, 5), (1031, 64, 1), (4096, 40, 33), (77, 16, 16)):
+        U = oracle.orth(rng.standard_normal((d, k)))
+        Z = oracle.orth(np.hstack([U, rng.standard_normal((d, r - k))])
+                        + 1e-3 * rng.standard_normal((d, r)))
+        g = lib.lp_sin_theta(torch.as_tensor(Z, device="cuda:0"), torch.as_tensor(U, device="cuda:0"))
+        o = oracle.sin_theta(Z, U)
+        assert abs(g - o) < 1e-12 * max(1.0, o) + 1e-6 * o

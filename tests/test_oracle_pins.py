@@ -369,3 +369,68 @@ def test_generator_spectrum_c1():
     w, A, U, lam = _c1()
     assert A.shape == (2000, 100) and w.A.dtype == torch.float64
     assert 4.0 < lam[4] / lam[5] < 8.0
+
+
+# ---------------------------------------------------------------- iteration rank r > k
+
+def _cluster(n=2400, d=60, k=4, r=8, seed=5):
+    """sigma_k close to sigma_{k+1}, a wide gap after sigma_r, noise-free, so
+    M = A^T A / n has eigenvalues sigma_j^2 exactly."""
+    sig = synth.spectrum_cluster(d, k, r)
+    A = synth.lowrank_plus_noise(n, d, sig, 0.0, seed).numpy()
+    lam, V = np.linalg.eigh(A.T @ A / n)
+    lam, V = lam[::-1], V[:, ::-1]
+    return A, lam, V[:, :k], sig
+
+
+def test_sin_theta_wider_iterate():
+    """Definition 1 with a d x r iterate: columns outside span(U) and its
+    complement's relevant directions leave the angles alone; a column along a
+    missing direction removes that angle."""
+    k = 3
+    th = np.array([0.3, 0.1, 0.2])
+    d = 4 * k
+    U = np.zeros((d, k)); U[:k] = np.eye(k)
+    Z = np.zeros((d, k + 2)); Z[:k, :k] = np.diag(np.cos(th)); Z[k:2 * k, :k] = np.diag(np.sin(th))
+    Z[3 * k, k] = 1.0; Z[3 * k + 1, k + 1] = 1.0          # unrelated extra directions
+    assert abs(oracle.sin_theta(Z, U) - np.sin(th).max()) < 1e-14
+    # adding e_{k+1}, the direction that z_1 leans into, puts e_1 into the span;
+    # an orthonormal basis of that span is e_{k+1}, z_2, z_3, e_1 (e_1 last, so a
+    # distance that read only the first k columns would see an angle of 90 degrees)
+    Z2 = np.zeros((d, k + 1)); Z2[:, 1:k] = Z[:, 1:k]; Z2[k, 0] = 1.0; Z2[0, k] = 1.0
+    assert np.abs(Z2.T @ Z2 - np.eye(k + 1)).max() < 1e-15
+    assert abs(oracle.sin_theta(Z2, U) - np.sin(th[1:]).max()) < 1e-14
+    Z3 = np.eye(d)[:, :2 * k]
+    assert oracle.sin_theta(Z3, U) < 1e-15
+
+
+def test_oversampled_rate():
+    """Iteration rank r above the target rank k (Algorithm 1's input; the
+    appendix on the eigengap): with p = 1 the run is subspace iteration, and
+    tan theta_k shrinks by lambda_{r+1} / lambda_k per round, so the gap that
+    matters is the one after lambda_r.  At rank k the same data converge at
+    lambda_{k+1} / lambda_k, here 0.97 per round."""
+    n, d, k, r, m = 2400, 60, 4, 8, 4
+    A, lam, Uk, sig = _cluster(n, d, k, r)
+    assert np.abs(lam - sig ** 2).max() < 1e-13 * lam[0]
+    offs = synth.equal_offsets(n, m)
+    Y0 = synth.gaussian_start(d, r, 5)
+    ro = oracle.localpower(A, offs, r, [1] * 16, "sign", Y0, U_ref=Uk)
+    tan = [x / math.sqrt(1 - x * x) for x in ro["sin_hist"]]
+    q = lam[r] / lam[k - 1]
+    for t in range(6, 13):
+        assert abs(tan[t + 1] / tan[t] / q - 1) < 0.02
+    rk = oracle.localpower(A, offs, k, [1] * 16, "sign", Y0[:, :k], U_ref=Uk)
+    assert rk["sin_hist"][-1] > 0.5 and ro["sin_hist"][-1] < 1e-11
+
+
+def test_oversampled_ritz_top_k():
+    """The top k Ritz pairs of the converged rank-r iterate are the top k
+    eigenpairs of M."""
+    n, d, k, r, m = 2400, 60, 4, 8, 4
+    A, lam, Uk, _ = _cluster(n, d, k, r)
+    ro = oracle.localpower(A, synth.equal_offsets(n, m), r, [1] * 30, "opt",
+                           synth.gaussian_start(d, r, 5))
+    rl, Zr, _ = oracle.ritz(A, ro["Z"])
+    assert np.abs(rl[:k] - lam[:k]).max() < 1e-13 * lam[0]
+    assert oracle.sin_theta(Zr[:, :k], Uk) < 1e-11
