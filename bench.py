@@ -183,6 +183,13 @@ def convergence(lp, P, w, k):
     for name, (sched, mode) in runs.items():
         h = lp.lp_run(P, k, sched, mode, w.Y0, U_ref=ref)["sin_hist"]
         out[name] = {"rounds_to": rounds_to(h), "final": float(h[-1]), "rounds": len(sched)}
+    # no schedule: the truth-free stop rule with p halving from 4 (lp_solve)
+    for mode in ("sign", "opt"):
+        g = lp.lp_solve(P, k, mode, w.Y0, 4, 1e-6, 200)
+        out[f"solve_{mode}_1e-6"] = {"status": g["status"], "rounds": g["stats"]["rounds"],
+                                     "local_iters": g["stats"]["local_iters"],
+                                     "p_used": [int(x) for x in g["p_used"]],
+                                     "final": lp.lp_sin_theta(g["Z"], ref)}
     return out
 
 

@@ -204,6 +204,44 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
                  const double* Y0, double* Z_out, double* ritz_out, const lp_run_opts* opts,
                  lp_run_stats* stats);
 
+/* Options of lp_solve; zero-initialise and set struct_size = sizeof(lp_solve_opts). */
+typedef struct {
+  int32_t struct_size;
+  int32_t p0;              /* local steps of the first round, >= 1 */
+  double target;           /* > 0: the run ends once the estimated distance of the p = 1
+                              iterates to their limit is at most target / 2 */
+  int32_t max_rounds;      /* >= 1 */
+  int32_t z0_orthonormal;  /* as in lp_run_opts */
+  int32_t* p_used;         /* host [max_rounds] or NULL: p of every round run */
+  double* change_out;      /* host [max_rounds] or NULL: c_r of every round run */
+} lp_solve_opts;
+
+typedef struct {
+  int32_t rounds, local_iters, breakdowns, near_singular;
+  int32_t p_final;         /* p of the last round run */
+  double change;           /* last c_r */
+  double estimate;         /* last E */
+  double ms_total;         /* duration of the rounds on the stream (HIP events) */
+} lp_solve_stats;
+
+/* LocalPower without a fixed schedule or a reference subspace: rounds start at
+ * p = p0 local steps and p decays on the data's own signal (the paper's advice to
+ * communicate rarely early and often late, Sections 3 and 5, turned into a rule;
+ * the rule itself is this library's).  After round r the change
+ * c_r = sin theta_k(Z_r, Z_{r-1}) (Definition 1) is measured on the device and read
+ * back (one synchronisation per round); q_r = c_r / c_{r-1} over rounds at the same
+ * p; with Q the larger of the last two such ratios, E = c_r Q / (1 - Q) estimates
+ * the distance to the limit of the current p (the tail of a geometric series).
+ * The iterates have settled when c_r == 0 or Q < 1 and E <= target / 2.  Settled at
+ * p = 1: the run ends with LP_OK.  Settled at p > 1, or q_r > 0.5 (a stall): p
+ * halves (the limit of a fixed p > 1 sits at an error floor, Corollary 1; p = 1
+ * has none).  After max_rounds rounds: LP_ENOTCONV, with Z_out (and ritz_out) from
+ * the last iterate and stats filled.  The serving layer applies the same rule to
+ * every job.  k, Y0, Z_out, ritz_out and stats as in lp_run (k is the iteration
+ * rank).  Synchronises the stream before returning. */
+lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, double* Z_out,
+                   double* ritz_out, const lp_solve_opts* opts, lp_solve_stats* stats);
+
 /* One local power iteration on every partition with a shared Z (the worker step
  * of DPI, Eq. (power_yi), without the 1/s_i scale):
  *   Z     : device d x k FP64 (rounded to the working precision of A's dtype);

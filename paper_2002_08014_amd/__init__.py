@@ -6,6 +6,8 @@ PyTorch supplies device memory and streams only.
 
 from ._lib import (  # noqa: F401
     LPError,
+    LP_OK,
+    LP_ENOTCONV,
     Problem,
     Server,
     load,
@@ -16,6 +18,7 @@ from ._lib import (  # noqa: F401
     lp_get_tuning,
     lp_autotune,
     lp_run,
+    lp_solve,
     lp_local_multiply,
     lp_orth,
     lp_align,

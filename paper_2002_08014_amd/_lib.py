@@ -23,7 +23,7 @@ DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
 MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
-           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_local_multiply", "lp_orth", "lp_align",
+           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_local_multiply", "lp_orth", "lp_align",
            "lp_sin_theta", "lp_sin_theta_r", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
            "lp_server_destroy")
@@ -53,6 +53,27 @@ class RunOpts(ctypes.Structure):
                 ("time_local", ctypes.c_int32),
                 ("split_rounds", ctypes.c_int32),
                 ("k_ref", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32),
+                ("p0", ctypes.c_int32),
+                ("target", ctypes.c_double),
+                ("max_rounds", ctypes.c_int32),
+                ("z0_orthonormal", ctypes.c_int32),
+                ("p_used", ctypes.POINTER(ctypes.c_int32)),
+                ("change_out", ctypes.POINTER(ctypes.c_double))]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32),
+                ("local_iters", ctypes.c_int32),
+                ("breakdowns", ctypes.c_int32),
+                ("near_singular", ctypes.c_int32),
+                ("p_final", ctypes.c_int32),
+                ("change", ctypes.c_double),
+                ("estimate", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
 
 
 class RunStats(ctypes.Structure):
@@ -127,6 +148,9 @@ def load() -> ctypes.CDLL:
     L.lp_autotune.restype = i32
     L.lp_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     L.lp_run.restype = i32
+    L.lp_solve.restype = i32
+    L.lp_solve.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                           ctypes.POINTER(SolveStats)]
     L.lp_run.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(RunOpts),
                          ctypes.POINTER(RunStats)]
     L.lp_local_multiply.restype = i32
@@ -313,6 +337,35 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
                     ctypes.byref(opts), ctypes.byref(stats)), "lp_run")
     return {"Z": Z, "ritz": rz, "sin_hist": hist, "signs": signs,
             "stats": {f: getattr(stats, f) for f, _ in RunStats._fields_}}
+
+
+def lp_solve(P: Problem, k: int, mode: str, Y0, p0: int, target: float, max_rounds: int,
+             ritz: bool = False, z0_orthonormal: bool = False):
+    """LocalPower with the truth-free stop rule and a decaying p (lp_solve).
+    Returns dict(Z, ritz, p_used, changes, stats, status); status is LP_OK when the
+    iterates settled at p = 1 and LP_ENOTCONV when max_rounds ran out (Z is then
+    the last iterate); other failures raise LPError."""
+    L = load()
+    dev = P.A.device
+    Y0d = _dev_f64(Y0, dev)
+    Z = torch.empty(P.d, k, dtype=torch.float64, device=dev)
+    rz = torch.empty(k, dtype=torch.float64, device=dev) if ritz else None
+    p_used = np.zeros(max_rounds, dtype=np.int32)
+    changes = np.zeros(max_rounds, dtype=np.float64)
+    o = SolveOpts()
+    o.struct_size = ctypes.sizeof(SolveOpts)
+    o.p0, o.target, o.max_rounds = int(p0), float(target), int(max_rounds)
+    o.z0_orthonormal = 1 if z0_orthonormal else 0
+    o.p_used = p_used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    o.change_out = changes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = SolveStats()
+    status = L.lp_solve(P.handle, k, MODES[mode], _ptr(Y0d), _ptr(Z), _ptr(rz), ctypes.byref(o),
+                        ctypes.byref(st))
+    if status not in (LP_OK, LP_ENOTCONV):
+        _check(status, "lp_solve")
+    n = st.rounds
+    return {"Z": Z, "ritz": rz, "p_used": p_used[:n], "changes": changes[:n], "status": status,
+            "stats": {f: getattr(st, f) for f, _ in SolveStats._fields_}}
 
 
 def lp_local_multiply(P: Problem, k: int, Z) -> torch.Tensor:

@@ -708,6 +708,7 @@ lp_status lp_destroy(lp_problem* P) {
   if (P->ev_join_out) (void)hipEventDestroy(P->ev_join_out);
   if (P->ev_t0) (void)hipEventDestroy(P->ev_t0);
   if (P->ev_t1) (void)hipEventDestroy(P->ev_t1);
+  if (P->change_host) (void)hipHostFree(P->change_host);
   delete P;
   return LP_OK;
 }
@@ -788,6 +789,22 @@ bool cache_lookup(const std::string& path, const std::string& key, lp_tuning* t)
     }
   }
   return found;
+}
+
+// Z_out = the current iterate, or with ritz_out its Rayleigh-Ritz rotation
+// after one p = 1 pass: Y = M Z, H = Z^T Y, H = Q diag(lam) Q^T, Z <- Z Q.
+hipError_t finish_z(lp_problem* P, int k, double* Z_out, double* ritz_out) {
+  Ptrs q = ptrs(P);
+  hipStream_t s = P->stream;
+  const int64_t d = P->d, dk = d * k;
+  hipError_t e;
+  if (ritz_out == nullptr) return hipMemcpyAsync(Z_out, q.Z, dk * 8, hipMemcpyDeviceToDevice, s);
+  if ((e = local_iter(P, k, q.Zw_shared, 0)) != hipSuccess) return e;
+  if ((e = launch_aggregate(P->m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, s)) != hipSuccess) return e;
+  if ((e = launch_cross_gram(1, d, k, q.Z, dk, q.Y, dk, q.gram, s)) != hipSuccess) return e;
+  if ((e = launch_sym_eig(P->plan.n_gram_chunks, k, q.gram, ritz_out, q.omat, s)) != hipSuccess)
+    return e;
+  return launch_right_mult(1, d, k, q.Z, q.omat, 0, false, Z_out, nullptr, 0, s);
 }
 
 void cache_store(const std::string& path, const std::string& key, const lp_tuning& t) {
@@ -1009,17 +1026,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   LP_HIP(hipEventRecord(P->ev_t1, s));
   if (timing) LP_HIP(drain_timing(P));
   P->timing = false;
-  if (ritz_out != nullptr) {
-    // one p = 1 pass: Y = M Z, H = Z^T Y, H = Q diag(lam) Q^T, Z <- Z Q
-    const int nch = P->plan.n_gram_chunks;
-    LP_HIP(local_iter(P, k, q.Zw_shared, 0));
-    LP_HIP(launch_aggregate(m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, s));
-    LP_HIP(launch_cross_gram(1, d, k, q.Z, dk, q.Y, dk, q.gram, s));
-    LP_HIP(launch_sym_eig(nch, k, q.gram, ritz_out, q.omat, s));
-    LP_HIP(launch_right_mult(1, d, k, q.Z, q.omat, 0, false, Z_out, nullptr, 0, s));
-  } else {
-    LP_HIP(hipMemcpyAsync(Z_out, q.Z, dk * 8, hipMemcpyDeviceToDevice, s));
-  }
+  LP_HIP(finish_z(P, k, Z_out, ritz_out));
   std::vector<int32_t> flags(m + 2, 0);
   LP_HIP(hipMemcpyAsync(flags.data(), q.flags, (m + 2) * 4, hipMemcpyDeviceToHost, s));
   LP_HIP(hipStreamSynchronize(s));
@@ -1041,6 +1048,79 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     stats->split_rounds = split ? 1 : 0;
   }
   if (breakdowns) return fail(LP_EBREAKDOWN, "Cholesky breakdown in an orthonormalisation");
+  return LP_OK;
+}
+
+lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, double* Z_out,
+                   double* ritz_out, const lp_solve_opts* opts, lp_solve_stats* stats) {
+  if (P == nullptr || Y0 == nullptr || Z_out == nullptr || opts == nullptr)
+    return fail(LP_EINVAL, "problem, Y0, Z_out and opts are required");
+  if (opts->struct_size < (int32_t)sizeof(lp_solve_opts))
+    return fail(LP_EINVAL, "opts->struct_size too small");
+  lp_status st = check_k(P, k);
+  if (st != LP_OK) return st;
+  if (mode != LP_AGG_VANILLA && mode != LP_AGG_SIGN && mode != LP_AGG_OPT)
+    return fail(LP_EINVAL, "unknown aggregation mode");
+  const lp_solve_opts& o = *opts;
+  if (o.p0 < 1 || !(o.target > 0.0) || o.max_rounds < 1)
+    return fail(LP_EINVAL, "need p0 >= 1, target > 0 and max_rounds >= 1");
+  if (P->change_host == nullptr) LP_HIP(hipHostMalloc((void**)&P->change_host, sizeof(double)));
+  Ptrs q = ptrs(P);
+  const int m = P->m;
+  const int64_t dk = P->d * k;
+  hipStream_t s = P->stream;
+  if ((st = drive_begin(P, k, Y0, o.z0_orthonormal != 0)) != LP_OK) return st;
+  // the previous iterate lives in the reference buffer (no reference here); the
+  // change of a round goes to the first history cell
+  LP_HIP(hipMemcpyAsync(q.Uref, q.Z, dk * 8, hipMemcpyDeviceToDevice, s));
+  LP_HIP(hipEventRecord(P->ev_t0, s));
+  StopRule rule;
+  rule.p = o.p0;
+  rule.target = o.target;
+  int rounds = 0, iters = 0;
+  bool settled = false, finite = true;
+  P->split_now = false;
+  while (rounds < o.max_rounds && !settled) {
+    const int p = rule.p;
+    if ((st = run_round(P, k, p, mode, 0, true, -1)) != LP_OK) return st;
+    LP_HIP(launch_sin_theta(P->d, k, k, q.Z, q.Uref, q.hist, nullptr, nullptr, s));
+    LP_HIP(hipMemcpyAsync(q.Uref, q.Z, dk * 8, hipMemcpyDeviceToDevice, s));
+    LP_HIP(hipMemcpyAsync(P->change_host, q.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+    LP_HIP(hipStreamSynchronize(s));
+    const double c = *P->change_host;
+    if (o.p_used != nullptr) o.p_used[rounds] = p;
+    if (o.change_out != nullptr) o.change_out[rounds] = c;
+    rounds++;
+    iters += p;
+    if (!std::isfinite(c)) {  // a breakdown left no valid iterate
+      finite = false;
+      break;
+    }
+    settled = rule.step(c);
+  }
+  LP_HIP(hipEventRecord(P->ev_t1, s));
+  LP_HIP(finish_z(P, k, Z_out, ritz_out));
+  std::vector<int32_t> flags(m + 2, 0);
+  LP_HIP(hipMemcpyAsync(flags.data(), q.flags, (m + 2) * 4, hipMemcpyDeviceToHost, s));
+  LP_HIP(hipStreamSynchronize(s));
+  if ((st = join_out(P)) != LP_OK) return st;
+  int breakdowns = 0;
+  for (int i = 0; i < m + 1; ++i) breakdowns += flags[i];
+  if (stats != nullptr) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, P->ev_t0, P->ev_t1);
+    stats->rounds = rounds;
+    stats->local_iters = iters;
+    stats->breakdowns = breakdowns;
+    stats->near_singular = flags[m + 1];
+    stats->p_final = rule.p_run;
+    stats->change = rule.change;
+    stats->estimate = rule.estimate;
+    stats->ms_total = ms;
+  }
+  if (breakdowns) return fail(LP_EBREAKDOWN, "Cholesky breakdown in an orthonormalisation");
+  if (!finite) return fail(LP_ENOTCONV, "the change between rounds is not finite");
+  if (!settled) return fail(LP_ENOTCONV, "not settled at p = 1 within max_rounds");
   return LP_OK;
 }
 

@@ -45,8 +45,8 @@ struct Job {
   double* zprev = nullptr;
   double* change_dev = nullptr;
   // schedule state
-  int p = 1, rounds = 0, iters = 0;
-  double prev_change = -1.0, prev_q = -1.0, change = 0.0, estimate = 0.0;
+  int rounds = 0, iters = 0;
+  lp::StopRule rule;
   bool in_flight = false;
 };
 
@@ -97,9 +97,9 @@ void publish(lp_server* S, Job* j, lp_status st) {
   r.status = st;
   r.rounds = j->rounds;
   r.local_iters = j->iters;
-  r.p_final = j->p;
-  r.change = j->change;
-  r.estimate = j->estimate;
+  r.p_final = j->rule.p_run;
+  r.change = j->rule.change;
+  r.estimate = j->rule.estimate;
   const Clock::time_point now = Clock::now();
   r.ms_queued = ms_between(j->t_submit, j->t_admit);
   r.ms_total = ms_between(j->t_submit, now);
@@ -143,7 +143,7 @@ lp_status launch(lp_server* S, Job* j) {
   lp_problem* P = j->P;
   hipStream_t s = lp::drive_stream(P);
   const int64_t dk = j->spec.d * j->spec.k;
-  lp_status st = lp::drive_round(P, j->spec.k, j->p, j->spec.mode);
+  lp_status st = lp::drive_round(P, j->spec.k, j->rule.p, j->spec.mode);
   if (st != LP_OK) return st;
   if (lp::launch_sin_theta(j->spec.d, j->spec.k, j->spec.k, lp::drive_z(P), j->zprev, j->change_dev, nullptr,
                            nullptr, s) != hipSuccess ||
@@ -184,7 +184,8 @@ lp_status start(lp_server* S, Job* j) {
   if (hipMemcpyAsync(j->zprev, lp::drive_z(j->P), (size_t)sp.d * sp.k * 8, hipMemcpyDeviceToDevice,
                      s) != hipSuccess)
     return lp::report(LP_EDEVICE, "serving: start copy failed");
-  j->p = sp.p0;
+  j->rule.p = sp.p0;
+  j->rule.target = sp.target;
   return launch(S, j);
 }
 
@@ -192,33 +193,17 @@ lp_status start(lp_server* S, Job* j) {
 // false when the job has ended (it is then published and deleted).
 bool advance(lp_server* S, Job* j) {
   j->in_flight = false;
-  j->change = S->pinned[j->slot];
+  const int p = j->rule.p;
   j->rounds++;
-  j->iters += j->p;
-  // contraction ratios of the changes at the current p; the estimate uses the
-  // larger of the last two (the first rounds after a change of p contract
-  // faster than the asymptotic rate and would underestimate the tail)
-  const double q = j->prev_change > 0.0 ? j->change / j->prev_change : -1.0;
-  const double qe = (q >= 0.0 && j->prev_q >= 0.0) ? std::max(q, j->prev_q) : -1.0;
-  const bool ratio = qe >= 0.0 && qe < 1.0;
-  j->estimate = ratio ? j->change * qe / (1.0 - qe) : j->change;
-  const bool settled = j->change == 0.0 || (ratio && j->estimate <= 0.5 * j->spec.target);
-  j->prev_q = q;
-  j->prev_change = j->change;
-  // settled at p = 1: done.  Settled at p > 1 only means the iterates reached
-  // the fixed point of this p, which sits at an error floor: halve p.
-  if (settled && j->p == 1) {
+  j->iters += p;
+  // settled at p = 1: done (settled at p > 1 or a stall halves p inside step)
+  if (j->rule.step(S->pinned[j->slot])) {
     finish(S, j, LP_OK);
     return false;
   }
   if (j->rounds >= j->spec.max_rounds) {
     finish(S, j, LP_ENOTCONV);
     return false;
-  }
-  if (j->p > 1 && (settled || q > 0.5)) {
-    j->p = std::max(1, j->p / 2);
-    j->prev_change = -1.0;
-    j->prev_q = -1.0;
   }
   lp_status st = launch(S, j);
   if (st != LP_OK) {

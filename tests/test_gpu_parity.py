@@ -398,3 +398,69 @@ def test_sin_theta_wider_iterate(lib):
         g = lib.lp_sin_theta(torch.as_tensor(Z, device="cuda:0"), torch.as_tensor(U, device="cuda:0"))
         o = oracle.sin_theta(Z, U)
         assert abs(g - o) < 1e-12 * max(1.0, o) + 1e-6 * o
+
+
+# --------------------------------------------------------------------- truth-free stop, decaying p
+
+def _rule_schedule(changes, p0, target):
+    """The stop rule as include/lp.h states it, applied to a list of changes:
+    returns the p of every round and whether the last round settled at p = 1."""
+    p, prev_c, prev_q, ps = p0, -1.0, -1.0, []
+    for c in changes:
+        ps.append(p)
+        q = c / prev_c if prev_c > 0 else -1.0
+        qe = max(q, prev_q) if (q >= 0 and prev_q >= 0) else -1.0
+        ratio = 0 <= qe < 1
+        est = c * qe / (1 - qe) if ratio else c
+        settled = c == 0 or (ratio and est <= 0.5 * target)
+        prev_q, prev_c = q, c
+        if settled and p == 1:
+            return ps, True
+        if p > 1 and (settled or q > 0.5):
+            p, prev_c, prev_q = max(1, p // 2), -1.0, -1.0
+    return ps, False
+
+
+@pytest.mark.parametrize("mode", ["sign", "opt"])
+def test_solve_against_oracle(lib, fp64_small, mode):
+    """lp_solve: every round's change sin theta(Z_r, Z_{r-1}) against the oracle
+    run round by round on the schedule the library chose, that schedule against
+    the stated rule applied to the oracle's changes, the final Z and Ritz pairs
+    against the oracle, and the final distance to the true subspace."""
+    w, A, U, lam = fp64_small
+    _flush(f"lp_solve {mode}")
+    target = 1e-8
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    g = lib.lp_solve(P, w.k, mode, w.Y0, 4, target, 200, ritz=True)
+    assert g["status"] == lib.LP_OK
+    ps = [int(x) for x in g["p_used"]]
+    assert ps[0] == 4 and ps[-1] == 1 and all(a >= b for a, b in zip(ps, ps[1:]))
+    Z = oracle.orth(w.Y0)
+    ch = []
+    for p in ps:
+        Zn = oracle.localpower(A, w.offsets, w.k, [p], mode, w.Y0, Z_init=Z)["Z"]
+        ch.append(oracle.sin_theta(Zn, Z))
+        Z = Zn
+    assert np.abs(np.array(ch) - g["changes"]).max() < 1e-10
+    ps_rule, done = _rule_schedule(ch, 4, target)
+    assert done and ps_rule == ps
+    lam_o, Zr_o, _ = oracle.ritz(A, Z)
+    assert np.abs(host(g["ritz"]) - lam_o).max() < 1e-10 * lam_o[0]
+    assert sin_theta_np(host(g["Z"]), Zr_o) < 1e-10
+    assert sin_theta_np(host(g["Z"]), U) < target
+    st = g["stats"]
+    assert st["rounds"] == len(ps) and st["local_iters"] == sum(ps) and st["p_final"] == 1
+    assert st["breakdowns"] == 0 and abs(st["change"] - ch[-1]) < 1e-10
+
+
+def test_solve_round_limit_and_arguments(lib, fp64_small):
+    w, A, U, lam = fp64_small
+    _flush("lp_solve limits")
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    g = lib.lp_solve(P, w.k, "opt", w.Y0, 4, 1e-12, 3)
+    assert g["status"] == lib.LP_ENOTCONV and g["stats"]["rounds"] == 3 and g["p_used"][0] == 4
+    ro = oracle.localpower(A, w.offsets, w.k, [int(x) for x in g["p_used"]], "opt", w.Y0)
+    assert np.abs(host(g["Z"]) - ro["Z"]).max() < 1e-10
+    for p0, target, rounds in ((0, 1e-6, 10), (4, 0.0, 10), (4, 1e-6, 0)):
+        with pytest.raises(lib.LPError):
+            lib.lp_solve(P, w.k, "opt", w.Y0, p0, target, rounds)
