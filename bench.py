@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--mode", default=None, choices=["sign", "opt", "vanilla"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--gram", action="store_true",
+                    help="local-Gram form: M_i = A_i^T A_i formed once (FP32/BF16 workloads)")
     ap.add_argument("--precision", action="store_true",
                     help="bf16 workload: both operand modes and both storage forms against FP64 runs")
     args = ap.parse_args()
@@ -338,6 +340,15 @@ def main():
     log("autotuning the local multiply")
     tuning = lp.lp_autotune(P, k)
     log(f"chosen {tuning}")
+    gram = None
+    if args.gram:
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        lp.lp_gram_enable(P)
+        torch.cuda.synchronize()
+        gram = {"setup_ms": round((time.perf_counter() - tg) * 1e3, 3),
+                "bytes_per_launch": w.m * d * d * 4}
+        log(f"Gram form on: {gram}")
     buf = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
     read_gbs = lp.lp_bandwidth_probe(buf, 5)
     copy_gbs = lp.lp_copy_probe(buf[1 << 30:], buf[:1 << 30], 5)
@@ -365,7 +376,12 @@ def main():
     flops_iter = 4.0 * n * d * k
     value = args.steps * iters_per_step * bytes_iter / el / 1e9
     k1_ms = ms_local / max(launches, 1)
-    if spec["bound"] == "hbm":
+    if gram is not None:
+        # the Gram form streams the m stacked d x d FP32 matrices per local multiply
+        achieved = gram["bytes_per_launch"] / (k1_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    elif spec["bound"] == "hbm":
         achieved = bytes_iter / (k1_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4)}
@@ -374,7 +390,7 @@ def main():
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MATRIX_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MATRIX_PEAK_TFS, 4),
                 "hbm_gbs": round(bytes_iter / (k1_ms / 1e3) / 1e9, 2)}
-    roof.update({"traffic": traffic_per_launch(spec), "kernel_ms": round(k1_ms, 5), "launches": launches,
+    roof.update({"traffic": None if gram else traffic_per_launch(spec), "kernel_ms": round(k1_ms, 5), "launches": launches,
                  "measured_read_gbs": round(read_gbs, 1), "measured_copy_gbs": round(copy_gbs, 1)})
     dtype = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float64: "f64"}[w.A.dtype]
     ps = sorted(set(sched), reverse=True)
@@ -393,7 +409,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"localpower {dtype} A {n}x{d}, k={k}, m={w.m} "
                                f"{'lognormal' if args.workload.startswith('fp32-uneven') else 'equal'} "
-                               f"partitions, p in {ps}, T={len(sched)} rounds, {w.mode} alignment",
+                               f"partitions, p in {ps}, T={len(sched)} rounds, {w.mode} alignment"
+                               + (", local-Gram form (value: A bytes per local iteration / time)"
+                                  if gram else ""),
                    "n": n, "d": d, "k": k, "m": w.m, "p_sched": sched if len(ps) > 1 else ps[0],
                    "rounds": len(sched), "local_iters_per_step": iters_per_step,
                    "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
@@ -401,6 +419,8 @@ def main():
                    "rounds_total": args.steps * len(sched)},
         "roofline": roof,
     }
+    if gram is not None:
+        out["config"]["gram"] = gram
     if not args.no_convergence and args.workload == "fp32-262144x1024":
         log("convergence (rounds to sin theta thresholds)")
         out["convergence"] = convergence(lp, P, w, k)

@@ -242,6 +242,27 @@ typedef struct {
 lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, double* Z_out,
                    double* ritz_out, const lp_solve_opts* opts, lp_solve_stats* stats);
 
+/* ---------------------------------------------------------------------------
+ * Local-Gram form of the local multiply.  Eq. (power_yi) costs O(d^2 k) per local
+ * iteration with M_i formed and O(s_i d k) without it.  lp_gram_enable computes M_i' = A_i^T A_i
+ * (d x d, FP32, one dense GEMM per partition through rocBLAS, on the problem's
+ * stream) into a caller-owned device buffer of lp_gram_bytes bytes; from then on
+ * every local multiply of the problem (lp_run, lp_solve, lp_local_multiply, the
+ * Ritz pass) computes Y_i = M_i' Z_i on the FP32 matrix cores, reading m d^2
+ * FP32 values instead of n d values of A.  It pays when m d is well below n (the
+ * HBM bytes per local multiply fall by n b / (4 m d) for b-byte A) and the run is
+ * long enough to amortise the 2 n d^2 flops of the Gram products.  The products
+ * round in FP32 (A^T A squares the condition of A; the top eigenvectors, not the
+ * small ones, are what the method needs).
+ *   requirements: FP32 or BF16 A, d % 4 == 0, m d <= n; buffer 256-byte aligned,
+ *   BORROWED until lp_gram_disable or lp_destroy, holding M_i' and a small work list.
+ *   Split rounds do not apply to this form; lp_autotune tunes the A form only.
+ * lp_gram_disable returns the problem to the A form (the buffer may then be freed).
+ * Both synchronise the problem's stream and drop its captured rounds. */
+lp_status lp_gram_bytes(const lp_problem* P, size_t* bytes);
+lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes);
+lp_status lp_gram_disable(lp_problem* P);
+
 /* One local power iteration on every partition with a shared Z (the worker step
  * of DPI, Eq. (power_yi), without the 1/s_i scale):
  *   Z     : device d x k FP64 (rounded to the working precision of A's dtype);

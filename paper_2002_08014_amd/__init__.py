@@ -19,6 +19,9 @@ from ._lib import (  # noqa: F401
     lp_autotune,
     lp_run,
     lp_solve,
+    lp_gram_bytes,
+    lp_gram_enable,
+    lp_gram_disable,
     lp_local_multiply,
     lp_orth,
     lp_align,

@@ -23,7 +23,8 @@ DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
 MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
-           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_local_multiply", "lp_orth", "lp_align",
+           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_gram_bytes",
+           "lp_gram_enable", "lp_gram_disable", "lp_local_multiply", "lp_orth", "lp_align",
            "lp_sin_theta", "lp_sin_theta_r", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
            "lp_server_destroy")
@@ -149,6 +150,12 @@ def load() -> ctypes.CDLL:
     L.lp_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     L.lp_run.restype = i32
     L.lp_solve.restype = i32
+    L.lp_gram_bytes.restype = i32
+    L.lp_gram_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.lp_gram_enable.restype = i32
+    L.lp_gram_enable.argtypes = [vp, vp, ctypes.c_size_t]
+    L.lp_gram_disable.restype = i32
+    L.lp_gram_disable.argtypes = [vp]
     L.lp_solve.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(SolveOpts),
                            ctypes.POINTER(SolveStats)]
     L.lp_run.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(RunOpts),
@@ -226,6 +233,7 @@ class Problem:
         self.offsets = offsets
         self.k_max = k_max
         self.stream = stream
+        self.gram_buffer = None   # device buffer of the local-Gram form while it is on
 
     @property
     def n(self):
@@ -266,6 +274,26 @@ def lp_create(A: torch.Tensor, offsets: Sequence[int], k_max: int,
                        offs.ctypes.data, len(offs) - 1, k_max, _ptr(ws), ws.numel(),
                        _stream_handle(st)), "lp_create")
     return Problem(h, A, ws, offs, k_max, st)
+
+
+def lp_gram_bytes(P: Problem) -> int:
+    nb = ctypes.c_size_t(0)
+    _check(load().lp_gram_bytes(P.handle, ctypes.byref(nb)), "lp_gram_bytes")
+    return int(nb.value)
+
+
+def lp_gram_enable(P: Problem) -> None:
+    """Switch the problem to the local-Gram form (M_i = A_i^T A_i formed once, FP32);
+    the buffer is a device tensor kept on the Problem."""
+    nb = lp_gram_bytes(P)
+    buf = torch.empty(max(nb, 256), dtype=torch.uint8, device=P.A.device)
+    _check(load().lp_gram_enable(P.handle, _ptr(buf), buf.numel()), "lp_gram_enable")
+    P.gram_buffer = buf
+
+
+def lp_gram_disable(P: Problem) -> None:
+    _check(load().lp_gram_disable(P.handle), "lp_gram_disable")
+    P.gram_buffer = None
 
 
 def lp_destroy(P: Problem) -> None:

@@ -275,4 +275,19 @@ hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda,
   return gemm_k<__hip_bfloat16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
 }
 
+hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void* Zw,
+                                int64_t z_stride, void* tbuf, const WorkItem* items, int m,
+                                hipStream_t s) {
+  // pass 1 alone over the stacked d x d matrices: item i covers rows i d .. i d + d - 1
+  dim3 g(m, (unsigned)((P.d + kBM1 - 1) / kBM1));
+  const float* Z = (const float*)Zw;
+  float* t = (float*)tbuf;
+  constexpr int MT = kBM1 / 64;
+  if (k <= 16) tmm_kernel<float, 1, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+  else if (k <= 32) tmm_kernel<float, 2, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+  else if (k <= 48) tmm_kernel<float, 3, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+  else tmm_kernel<float, 4, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+  return hipGetLastError();
+}
+
 }  // namespace lp

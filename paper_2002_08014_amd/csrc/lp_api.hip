@@ -1,6 +1,8 @@
 // C ABI of the LocalPower library: problem handle, workspace layout, the
 // round driver (Algorithm 1 with sign-fixing / OPT alignment) and its hipGraph
 // replay.  Host code only; the kernels live in k_local.hip and k_small.hip.
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -270,13 +272,20 @@ hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
     P->ev_used++;
     if ((e = hipEventRecord(ev0, P->stream)) != hipSuccess) return e;
   }
-  e = launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, p.tbuf, p.part, p.items,
-                            (int)P->plan.items.size(), P->stream);
+  if (P->gram_on)
+    e = launch_gram_multiply(P->plan, P->gram_M, k, zsrc, zstride, p.tbuf, P->gram_items, P->m,
+                             P->stream);
+  else
+    e = launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, p.tbuf, p.part, p.items,
+                              (int)P->plan.items.size(), P->stream);
   if (e != hipSuccess) return e;
   if (ev1 != nullptr) {
     e = (P->timing_slot >= 0) ? capture_event_node(P->stream, ev1) : hipEventRecord(ev1, P->stream);
     if (e != hipSuccess) return e;
   }
+  if (P->gram_on)  // one FP32 "partial" per partition: Y_i itself
+    return launch_reduce_gram(P->plan, k, p.tbuf, P->gram_slot_off, p.Yi, p.gram, 0, P->m,
+                              P->stream);
   return launch_reduce_gram(P->plan, k, p.part, p.slot_off, p.Yi, p.gram, 0, P->m, P->stream);
 }
 
@@ -709,6 +718,7 @@ lp_status lp_destroy(lp_problem* P) {
   if (P->ev_t0) (void)hipEventDestroy(P->ev_t0);
   if (P->ev_t1) (void)hipEventDestroy(P->ev_t1);
   if (P->change_host) (void)hipHostFree(P->change_host);
+  if (P->blas) (void)rocblas_destroy_handle((rocblas_handle)P->blas);
   delete P;
   return LP_OK;
 }
@@ -932,7 +942,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     const bool fused =
         (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, P->d, P->lda, k)) ||
         (P->plan.path == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, P->d, P->lda, k, P->A));
-    split = P->can_split && (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
+    split = P->can_split && !P->gram_on && (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
   }
   if (split && P->stream2 == nullptr) {
     // the second stream and its events exist only in problems that run split
@@ -1124,6 +1134,96 @@ lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, doub
   return LP_OK;
 }
 
+lp_status lp_gram_bytes(const lp_problem* P, size_t* bytes) {
+  if (P == nullptr || bytes == nullptr) return fail(LP_EINVAL, "NULL argument");
+  const size_t d = (size_t)P->d, m = (size_t)P->m;
+  *bytes = align256(m * d * d * 4) + align256(m * sizeof(WorkItem)) + align256((m + 1) * 4);
+  return LP_OK;
+}
+
+lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes) {
+  if (P == nullptr || buffer == nullptr) return fail(LP_EINVAL, "NULL argument");
+  if (((uintptr_t)buffer & 255) != 0) return fail(LP_EINVAL, "buffer must be 256-byte aligned");
+  size_t need = 0;
+  lp_gram_bytes(P, &need);
+  if (bytes < need) return fail(LP_EINVAL, "buffer smaller than lp_gram_bytes");
+  if (P->dtype != LP_F32 && P->dtype != LP_BF16)
+    return fail(LP_EINVAL, "the Gram form takes FP32 or BF16 A");
+  if (P->d % 4 != 0) return fail(LP_EINVAL, "the Gram form needs d % 4 == 0");
+  if ((int64_t)P->m * P->d > P->n)
+    return fail(LP_EINVAL, "the Gram form needs m d <= n (it would move more bytes than A)");
+  const int64_t d = P->d;
+  const int m = P->m;
+  char* b = (char*)buffer;
+  float* M = (float*)b;
+  WorkItem* items = (WorkItem*)(b + align256((size_t)m * d * d * 4));
+  int32_t* slot_off = (int32_t*)((char*)items + align256((size_t)m * sizeof(WorkItem)));
+  if (P->blas == nullptr) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      return fail(LP_EDEVICE, "rocblas_create_handle failed");
+    P->blas = h;
+  }
+  rocblas_handle h = (rocblas_handle)P->blas;
+  if (rocblas_set_stream(h, P->stream) != rocblas_status_success)
+    return fail(LP_EDEVICE, "rocblas_set_stream failed");
+  lp_status st;
+  if ((st = join_in(P)) != LP_OK) return st;
+  // M_i = A_i^T A_i: the row-major s_i x d block A_i is the column-major d x s_i
+  // matrix X = A_i^T (leading dimension lda), and M_i = X X^T (symmetric, so its
+  // row- and column-major forms agree)
+  const float one = 1.f, zero = 0.f;
+  for (int i = 0; i < m; ++i) {
+    const int64_t s_i = P->offsets[i + 1] - P->offsets[i];
+    float* Mi = M + (size_t)i * d * d;
+    rocblas_status rs;
+    if (P->dtype == LP_F32) {
+      const float* X = (const float*)P->A + P->offsets[i] * P->lda;
+      rs = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)d,
+                         (rocblas_int)d, (rocblas_int)s_i, &one, X, (rocblas_int)P->lda, X,
+                         (rocblas_int)P->lda, &zero, Mi, (rocblas_int)d);
+    } else {
+      const __hip_bfloat16* X = (const __hip_bfloat16*)P->A + P->offsets[i] * P->lda;
+      rs = rocblas_gemm_ex(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)d,
+                           (rocblas_int)d, (rocblas_int)s_i, &one, X, rocblas_datatype_bf16_r,
+                           (rocblas_int)P->lda, X, rocblas_datatype_bf16_r, (rocblas_int)P->lda,
+                           &zero, Mi, rocblas_datatype_f32_r, (rocblas_int)d, Mi,
+                           rocblas_datatype_f32_r, (rocblas_int)d, rocblas_datatype_f32_r,
+                           rocblas_gemm_algo_standard, 0, 0);
+    }
+    if (rs != rocblas_status_success)
+      return fail(LP_EDEVICE, std::string("Gram product: ") + rocblas_status_to_string(rs));
+  }
+  std::vector<WorkItem> hi(m);
+  std::vector<int32_t> ho(m + 1);
+  for (int i = 0; i < m; ++i) hi[i] = WorkItem{i, i, (int64_t)i * d, d};
+  for (int i = 0; i <= m; ++i) ho[i] = i;
+  LP_HIP(hipMemcpyAsync(items, hi.data(), m * sizeof(WorkItem), hipMemcpyHostToDevice, P->stream));
+  LP_HIP(hipMemcpyAsync(slot_off, ho.data(), (m + 1) * 4, hipMemcpyHostToDevice, P->stream));
+  LP_HIP(hipStreamSynchronize(P->stream));
+  // captured rounds launch the other form's kernels
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  P->graphs.clear();
+  P->gram_M = M;
+  P->gram_items = items;
+  P->gram_slot_off = slot_off;
+  P->gram_on = true;
+  return join_out(P);
+}
+
+lp_status lp_gram_disable(lp_problem* P) {
+  if (P == nullptr) return fail(LP_EINVAL, "NULL argument");
+  if (!P->gram_on) return LP_OK;
+  LP_HIP(hipStreamSynchronize(P->stream));
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  P->graphs.clear();
+  P->gram_on = false;
+  P->gram_M = nullptr;
+  P->gram_items = nullptr;
+  P->gram_slot_off = nullptr;
+  return LP_OK;
+}
+
 lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y_out) {
   if (P == nullptr || Z == nullptr || Y_out == nullptr) return fail(LP_EINVAL, "NULL argument");
   lp_status st = check_k(P, k);
@@ -1131,6 +1231,12 @@ lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y
   Ptrs q = ptrs(P);
   if ((st = join_in(P)) != LP_OK) return st;
   LP_HIP(launch_to_working(P->plan, 1, P->d, k, Z, q.Zw_shared, P->stream));
+  if (P->gram_on) {
+    LP_HIP(launch_gram_multiply(P->plan, P->gram_M, k, q.Zw_shared, 0, q.tbuf, P->gram_items, P->m,
+                                P->stream));
+    LP_HIP(launch_reduce_partials(P->plan, k, q.tbuf, P->gram_slot_off, Y_out, P->stream));
+    return join_out(P);
+  }
   LP_HIP(launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
                                (int)P->plan.items.size(), P->stream));
   LP_HIP(launch_reduce_partials(P->plan, k, q.part, q.slot_off, Y_out, P->stream));

@@ -157,6 +157,12 @@ struct lp_problem {
   bool split_now = false;   // the rounds being enqueued are split
   lp::Half half[2];
   double* change_host = nullptr;   // pinned cell for lp_solve's per-round change
+  // local-Gram form (lp_gram_enable): M_i = A_i^T A_i in a caller-owned buffer
+  bool gram_on = false;
+  float* gram_M = nullptr;
+  lp::WorkItem* gram_items = nullptr;
+  int32_t* gram_slot_off = nullptr;
+  void* blas = nullptr;            // rocBLAS handle for the one-time Gram products
 };
 
 namespace lp {
@@ -205,6 +211,12 @@ hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t ld
 // Two-pass form on FP32 matrix cores (t = A Z, then A^T t): FP32 or BF16 A,
 // d % 4 == 0, any k <= 64.
 bool gemm_eligible(lp_dtype dtype, int64_t d, int64_t lda, const void* A);
+// Local-Gram form: Y_i = M_i Z_i for the m stacked FP32 d x d matrices M_i = A_i^T A_i
+// (row-major, M_i at M + i d d); items[i] = {i, i, i d, d}; writes Y_i (FP32) to
+// tbuf + i d k.
+hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void* Zw,
+                                int64_t z_stride, void* tbuf, const WorkItem* items, int m,
+                                hipStream_t s);
 hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                       const WorkItem* items, int nitems,
