@@ -193,6 +193,30 @@ def convergence(lp, P, w, k):
     return out
 
 
+def trends(lp, synth, w, k, rounds=40, ms=(8, 32, 128), ps=(1, 2, 4, 8, 16)):
+    """sin theta after `rounds` rounds of fixed p (the error floor once p > 1) for
+    several uniform partitionings of the same matrix, with eta of each partitioning
+    (the paper's experiments on p and m; Corollary 1: the floor grows with p and
+    with m, and OPT keeps it lower).  The reference is a long p = 1 run refined by
+    Rayleigh-Ritz.  Runs through the local-Gram form (same method, fewer bytes)."""
+    out = {}
+    ref = None
+    for m in ms:
+        offs = synth.equal_offsets(w.n, m)
+        P = lp.lp_create(w.A, offs, k)
+        lp.lp_gram_enable(P)
+        if ref is None:
+            ref = lp.lp_run(P, k, [1] * 150, "sign", w.Y0, ritz=True)["Z"]
+        eta, _ = lp.lp_eta(P, 300)
+        row = {"eta": round(eta, 5)}
+        for mode in ("sign", "opt"):
+            row[mode] = {str(p): float(lp.lp_run(P, k, [p] * rounds, mode, w.Y0, U_ref=ref)["sin_hist"][-1])
+                         for p in ps}
+        out[f"m={m}"] = row
+        lp.lp_destroy(P)
+    return out
+
+
 def make_job_mix(n_jobs, seed, device):
     """Seeded serving job list: d in {256, 512, 1024, 2048}, n = B d with B in
     [16, 64], m in {4, 16}, FP32 (k in {4, 8, 16, 32}) or BF16 (k in {4, 8, 12}),
@@ -312,6 +336,9 @@ def main():
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--gram", action="store_true",
                     help="local-Gram form: M_i = A_i^T A_i formed once (FP32/BF16 workloads)")
+    ap.add_argument("--trends", action="store_true",
+                    help="default workload: error floors over p and m and eta (Definition 2), "
+                         "through the local-Gram form")
     ap.add_argument("--precision", action="store_true",
                     help="bf16 workload: both operand modes and both storage forms against FP64 runs")
     args = ap.parse_args()
@@ -424,6 +451,9 @@ def main():
     if not args.no_convergence and args.workload == "fp32-262144x1024":
         log("convergence (rounds to sin theta thresholds)")
         out["convergence"] = convergence(lp, P, w, k)
+    if args.trends and args.workload == "fp32-262144x1024":
+        log("floors over p and m")
+        out["trends"] = trends(lp, synth, w, k)
     if args.precision and args.workload == "bf16-1048576x2048":
         out["precision"] = precision_report(lp, synth, w, P, tuning, sched)
     if not args.no_cpu_baseline:

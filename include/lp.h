@@ -263,6 +263,16 @@ lp_status lp_gram_bytes(const lp_problem* P, size_t* bytes);
 lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes);
 lp_status lp_gram_disable(lp_problem* P);
 
+/* eta = max_i ||M_i - M||_2 / ||M||_2 (Definition 2: how far the local matrices
+ * M_i = A_i^T A_i / s_i are from M = A^T A / n; the analysis' error floor grows with
+ * it).  Needs the local-Gram form (its FP32 M_i'); M is summed in FP64 and each
+ * spectral norm is estimated by `iters` steps of power iteration from four fixed
+ * pseudo-random start vectors (an estimate from below that converges at the rate
+ * (lambda_2 / lambda_1)^2 per step).  eta_out: host double; per_part_out: host [m]
+ * ||M_i - M||_2 / ||M||_2, or NULL.  Allocates and frees device scratch of about
+ * 8 d^2 + 64 (m + 1) d bytes and synchronises the stream. */
+lp_status lp_eta(lp_problem* P, int32_t iters, double* eta_out, double* per_part_out);
+
 /* One local power iteration on every partition with a shared Z (the worker step
  * of DPI, Eq. (power_yi), without the 1/s_i scale):
  *   Z     : device d x k FP64 (rounded to the working precision of A's dtype);

@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401
     lp_gram_bytes,
     lp_gram_enable,
     lp_gram_disable,
+    lp_eta,
     lp_local_multiply,
     lp_orth,
     lp_align,

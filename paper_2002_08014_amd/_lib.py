@@ -24,7 +24,7 @@ MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_gram_bytes",
-           "lp_gram_enable", "lp_gram_disable", "lp_local_multiply", "lp_orth", "lp_align",
+           "lp_gram_enable", "lp_gram_disable", "lp_eta", "lp_local_multiply", "lp_orth", "lp_align",
            "lp_sin_theta", "lp_sin_theta_r", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
            "lp_server_destroy")
@@ -155,6 +155,8 @@ def load() -> ctypes.CDLL:
     L.lp_gram_enable.restype = i32
     L.lp_gram_enable.argtypes = [vp, vp, ctypes.c_size_t]
     L.lp_gram_disable.restype = i32
+    L.lp_eta.restype = i32
+    L.lp_eta.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.lp_gram_disable.argtypes = [vp]
     L.lp_solve.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(SolveOpts),
                            ctypes.POINTER(SolveStats)]
@@ -294,6 +296,15 @@ def lp_gram_enable(P: Problem) -> None:
 def lp_gram_disable(P: Problem) -> None:
     _check(load().lp_gram_disable(P.handle), "lp_gram_disable")
     P.gram_buffer = None
+
+
+def lp_eta(P: Problem, iters: int = 300):
+    """(eta, per-partition ||M_i - M|| / ||M||) of Definition 2; needs lp_gram_enable."""
+    out = ctypes.c_double(0.0)
+    per = np.zeros(P.m, dtype=np.float64)
+    _check(load().lp_eta(P.handle, int(iters), ctypes.byref(out),
+                         per.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "lp_eta")
+    return float(out.value), per
 
 
 def lp_destroy(P: Problem) -> None:

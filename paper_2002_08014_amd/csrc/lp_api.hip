@@ -1224,6 +1224,39 @@ lp_status lp_gram_disable(lp_problem* P) {
   return LP_OK;
 }
 
+lp_status lp_eta(lp_problem* P, int32_t iters, double* eta_out, double* per_part_out) {
+  if (P == nullptr || eta_out == nullptr) return fail(LP_EINVAL, "NULL argument");
+  if (!P->gram_on) return fail(LP_EINVAL, "lp_eta needs the local-Gram form (lp_gram_enable)");
+  if (iters < 1) return fail(LP_EINVAL, "need iters >= 1");
+  const int m = P->m;
+  const int nb = eta_start_vectors();
+  std::vector<double> inv_s(m), est((size_t)(m + 1) * nb);
+  for (int i = 0; i < m; ++i) inv_s[i] = 1.0 / (double)(P->offsets[i + 1] - P->offsets[i]);
+  char* scratch = nullptr;
+  lp_status st;
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(hipStreamSynchronize(P->stream));
+  LP_HIP(hipMalloc((void**)&scratch, eta_scratch_bytes(P->d, m)));
+  hipError_t e = launch_eta(P->d, m, P->n, P->gram_M, inv_s.data(), iters, scratch, est.data(),
+                            P->stream);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return fail(LP_EDEVICE, std::string("eta: ") + hipGetErrorString(e));
+  auto row_max = [&](int b) {
+    double v = 0.0;
+    for (int j = 0; j < nb; ++j) v = std::max(v, est[(size_t)b * nb + j]);
+    return v;
+  };
+  const double mn = row_max(m);
+  double eta = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double v = mn > 0.0 ? row_max(i) / mn : 0.0;
+    if (per_part_out != nullptr) per_part_out[i] = v;
+    eta = std::max(eta, v);
+  }
+  *eta_out = eta;
+  return join_out(P);
+}
+
 lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y_out) {
   if (P == nullptr || Z == nullptr || Y_out == nullptr) return fail(LP_EINVAL, "NULL argument");
   lp_status st = check_k(P, k);

@@ -211,6 +211,13 @@ hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t ld
 // Two-pass form on FP32 matrix cores (t = A Z, then A^T t): FP32 or BF16 A,
 // d % 4 == 0, any k <= 64.
 bool gemm_eligible(lp_dtype dtype, int64_t d, int64_t lda, const void* A);
+// Definition 2 diagnostics on the local-Gram form's matrices: scratch bytes, and
+// est_host[(m + 1) x eta_start_vectors()] = power-iteration estimates of
+// ||M_i'/s_i - M||_2 (rows 0..m-1) and ||M||_2 (row m) after `iters` steps.
+size_t eta_scratch_bytes(int64_t d, int m);
+hipError_t launch_eta(int64_t d, int m, int64_t n, const float* Mi, const double* inv_s_host,
+                      int iters, char* scratch, double* est_host, hipStream_t s);
+int eta_start_vectors();
 // Local-Gram form: Y_i = M_i Z_i for the m stacked FP32 d x d matrices M_i = A_i^T A_i
 // (row-major, M_i at M + i d d); items[i] = {i, i, i d, d}; writes Y_i (FP32) to
 // tbuf + i d k.

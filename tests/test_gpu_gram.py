@@ -124,3 +124,24 @@ def test_gram_refusals(lp):
     P = lp.lp_create(w.A, w.offsets, 4)
     with pytest.raises(lp.LPError):
         lp.lp_gram_enable(P)                       # d % 4 != 0
+
+
+@pytest.mark.parametrize("m", [4, 16])
+def test_eta_against_oracle(lp, m):
+    """eta (Definition 2) from the Gram form's matrices against the oracle's
+    dense spectral norms on the same stored FP32 values."""
+    print(f"eta m={m}", flush=True)
+    w = synth.make_small(8192, 64, 4, m, seed=m, dtype=torch.float32, noise=0.05, device="cuda:0")
+    P = lp.lp_create(w.A, w.offsets, 4)
+    with pytest.raises(lp.LPError):
+        lp.lp_eta(P)                               # needs the Gram form
+    lp.lp_gram_enable(P)
+    eta, per = lp.lp_eta(P, 400)
+    A = upcast(w.A)
+    n = A.shape[0]
+    Mm = A.T @ A / n
+    nm = np.linalg.norm(Mm, 2)
+    per_o = [np.linalg.norm(A[w.offsets[i]:w.offsets[i + 1]].T @ A[w.offsets[i]:w.offsets[i + 1]]
+                            / (w.offsets[i + 1] - w.offsets[i]) - Mm, 2) / nm for i in range(m)]
+    assert abs(eta - oracle.eta(A, w.offsets)) < 1e-3 * eta
+    assert np.abs(per - np.array(per_o)).max() < 1e-3 * max(per_o)

@@ -434,3 +434,26 @@ def test_oversampled_ritz_top_k():
     rl, Zr, _ = oracle.ritz(A, ro["Z"])
     assert np.abs(rl[:k] - lam[:k]).max() < 1e-13 * lam[0]
     assert oracle.sin_theta(Zr[:, :k], Uk) < 1e-11
+
+
+# ---------------------------------------------------------------- eta (Definition 2)
+
+def test_eta_closed_form():
+    """Two partitions along the axes: s1 rows [a, 0], s2 rows [0, b] give
+    M_1 = diag(a^2, 0), M_2 = diag(0, b^2), M = diag(p1 a^2, p2 b^2), so
+    eta = max(|M_1 - M|, |M_2 - M|) / |M| in closed form (diagonal matrices)."""
+    for a, b, s1, s2 in ((2.0, 1.0, 25, 75), (1.0, 2.0, 25, 75), (1.0, 1.0, 50, 50), (3.0, 0.5, 10, 90)):
+        A = np.vstack([np.tile([a, 0.0], (s1, 1)), np.tile([0.0, b], (s2, 1))])
+        p1, p2 = s1 / (s1 + s2), s2 / (s1 + s2)
+        Mn = max(p1 * a * a, p2 * b * b)
+        e1 = max(a * a * (1 - p1), p2 * b * b)
+        e2 = max(p1 * a * a, b * b * (1 - p2))
+        assert abs(oracle.eta(A, [0, s1, s1 + s2]) - max(e1, e2) / Mn) < 1e-14 * max(e1, e2) / Mn
+
+
+def test_eta_grows_with_m():
+    """Uniform partitions of one matrix: smaller local samples (larger m) put the
+    local matrices further from M (the paper's local-sample-size experiment)."""
+    A = synth.lowrank_plus_noise(4096, 32, synth.spectrum_c1(32, 4), 0.05, 11).numpy()
+    e = [oracle.eta(A, synth.equal_offsets(4096, m)) for m in (2, 8, 32)]
+    assert e[0] < e[1] < e[2]
