@@ -166,6 +166,12 @@ typedef struct {
                             r >= target rank) and sin_hist records sin theta_{k_ref}(Z_r,
                             U_ref) = ||(I - Z_r Z_r^T) U_ref|| with Z_r of k columns (the
                             distance of the appendix on the eigengap, Theorem there) */
+  double* rho_out;       /* host [T] or NULL: the residual error of Definition 3 at each
+                            round's last local step (its largest in the round), measured on
+                            the inputs of that step against the first partition's:
+                            max_i ||Z_i - Z_1||_2, or with OPT max_i min_O ||Z_i O - Z_1||_2
+                            = 2 sin(theta_max(Z_i, Z_1) / 2); 0 for rounds with p = 1.
+                            Rounds then run on one stream. */
 } lp_run_opts;
 
 typedef struct {

@@ -15,7 +15,11 @@ Pins (checked by the CPU test-suite against mathematics, not against itself):
   * OPT satisfies the closed form of the Procrustes lemma and undoes
     injected rotations exactly;
   * the cyclic Jacobi eigensolver equals LAPACK and the truth on tiny d;
-  * Ritz values at convergence equal the top eigenvalues of M.
+  * Ritz values at convergence equal the top eigenvalues of M;
+  * the rank-r iterate converges at lambda_{r+1} / lambda_k (subspace iteration);
+  * eta has a closed form on axis-aligned partitions;
+  * the OPT residual error equals a brute-force minimum over rotations and
+    2 sin(theta_max / 2).
 Qualitative behaviours (error floors growing with p, decay reaching DPI
 precision, vanilla instability) are checked as trends only: parity unpinned
 for the exact values of p > 1 runs on large workloads, which only the
@@ -35,6 +39,7 @@ from .localpower import (  # noqa: F401
     projection_distance,
     ritz,
     eta,
+    residual_error,
 )
 from .jacobi import jacobi_eig  # noqa: F401
 from .truth import top_k  # noqa: F401

@@ -90,6 +90,20 @@ def projection_distance(Z: np.ndarray, U: np.ndarray) -> float:
     return float(np.linalg.norm(Z @ Z.T - U @ U.T, 2))
 
 
+def residual_error(Z_list: Sequence[np.ndarray], use_opt: bool) -> float:
+    """rho (Definition 3) of a set of local iterates: max_i ||Z_i - Z_1||_2 without
+    OPT, max_i min_O ||Z_i O - Z_1||_2 over orthogonal O with OPT.  The minimiser
+    is the polar factor of Z_i^T Z_1 (the Procrustes rotation of Eq. (opt:o)),
+    which minimises the spectral distance too for matrices with orthonormal
+    columns."""
+    Z1 = Z_list[0]
+    out = 0.0
+    for Zi in Z_list:
+        D = Zi @ opt_matrix(Zi, Z1) - Z1 if use_opt else Zi - Z1
+        out = max(out, float(np.linalg.norm(D, 2)))
+    return out
+
+
 def _blocks(A: np.ndarray, offsets: Sequence[int]) -> List[np.ndarray]:
     o = np.asarray(offsets, dtype=np.int64)
     return [A[o[i]:o[i + 1]] for i in range(len(o) - 1)]
@@ -113,7 +127,8 @@ def localpower(A: np.ndarray, offsets: Sequence[int], k: int, p_sched: Sequence[
     The start is Z = orth(Y0) (Algorithm 1, initialisation), unless Z_init
     supplies an already orthonormal start.
 
-    Returns a dict with Z, per-round sign vectors, ambiguity counts and
+    Returns a dict with Z, per-round sign vectors, ambiguity counts, the
+    residual error rho (Definition 3) of each round's last local step and
     (when U_ref is given) the per-round sin theta history.
     """
     if mode not in ("vanilla", "sign", "opt"):
@@ -126,6 +141,7 @@ def localpower(A: np.ndarray, offsets: Sequence[int], k: int, p_sched: Sequence[
     blocks = _blocks(A, offsets)
     Z = np.array(Z_init, dtype=np.float64) if Z_init is not None else orth(np.asarray(Y0, np.float64))
     hist: List[float] = []
+    rho: List[float] = []
     signs: List[Optional[np.ndarray]] = []
     ambiguous = 0
     local_iters = 0
@@ -142,6 +158,8 @@ def localpower(A: np.ndarray, offsets: Sequence[int], k: int, p_sched: Sequence[
             local_iters += 1
             if step < p:
                 Zi = [local_orth(V[i]) for i in range(m)]
+        # residual error at the last local step (the largest of the round; 0 at p = 1)
+        rho.append(residual_error(Zlast, mode == "opt"))
         if p == 1 or mode == "vanilla":
             D = [np.eye(k) for _ in range(m)]
             signs.append(None)
@@ -159,7 +177,7 @@ def localpower(A: np.ndarray, offsets: Sequence[int], k: int, p_sched: Sequence[
         Z = orth(Y)
         if U_ref is not None:
             hist.append(sin_theta(Z, U_ref))
-    return {"Z": Z, "Y": Y, "sin_hist": hist, "signs": signs, "ambiguous": ambiguous,
+    return {"Z": Z, "Y": Y, "sin_hist": hist, "rho": rho, "signs": signs, "ambiguous": ambiguous,
             "rounds": len(p_sched), "local_iters": local_iters, "base": b}
 
 

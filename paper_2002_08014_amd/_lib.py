@@ -53,7 +53,8 @@ class RunOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32),
                 ("time_local", ctypes.c_int32),
                 ("split_rounds", ctypes.c_int32),
-                ("k_ref", ctypes.c_int32)]
+                ("k_ref", ctypes.c_int32),
+                ("rho_out", ctypes.POINTER(ctypes.c_double))]
 
 
 class SolveOpts(ctypes.Structure):
@@ -338,13 +339,14 @@ def lp_autotune(P: Problem, k: int, cache_path: Optional[str] = None) -> dict:
 def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool = False,
            U_ref: Optional[torch.Tensor] = None, record_signs: bool = False,
            z0_orthonormal: bool = False, use_graph: bool = True, time_local: int = 0,
-           split_rounds: Optional[bool] = None):
+           split_rounds: Optional[bool] = None, record_rho: bool = False):
     """Returns dict(Z, ritz, sin_hist, signs, stats); Z is a device d x k float64 tensor.
     time_local: 0 no events, 1 (or True) every local multiply timed, 2 the first
     one of every round only.  split_rounds: partitions in two halves on two streams
     (None: the library decides, True: always, False: never).  k is the iteration
     rank; U_ref may have fewer columns (the target rank), and sin_hist then holds
-    sin theta of the rank-k iterate against it."""
+    sin theta of the rank-k iterate against it.  record_rho: the residual error of
+    Definition 3 at every round's last local step (rho)."""
     L = load()
     dev = P.A.device
     sched = np.ascontiguousarray(np.asarray(p_sched, dtype=np.int32))
@@ -367,6 +369,10 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
         opts.U_ref = Ud.data_ptr()
         opts.k_ref = Ud.shape[1]
         opts.sin_hist = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rho = None
+    if record_rho:
+        rho = np.zeros(T, dtype=np.float64)
+        opts.rho_out = rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     signs = None
     if record_signs:
         signs = np.zeros((T, P.m, k), dtype=np.int8)
@@ -374,7 +380,7 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
     stats = RunStats()
     _check(L.lp_run(P.handle, k, sched.ctypes.data, T, MODES[mode], _ptr(Y0d), _ptr(Z), _ptr(rz),
                     ctypes.byref(opts), ctypes.byref(stats)), "lp_run")
-    return {"Z": Z, "ritz": rz, "sin_hist": hist, "signs": signs,
+    return {"Z": Z, "ritz": rz, "sin_hist": hist, "rho": rho, "signs": signs,
             "stats": {f: getattr(stats, f) for f, _ in RunStats._fields_}}
 
 

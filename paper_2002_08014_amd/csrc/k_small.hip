@@ -870,13 +870,16 @@ sym_eig_kernel(int nchunks, int k, const double* __restrict__ part, double* __re
 }
 
 // ---------------------------------------------------------------------------
-// sin theta_k(Z, U) = sqrt(lambda_max(W^T W)), W = U - Z (Z^T U); one workgroup.
-// Z is d x r (the iterate, r >= k columns), U is d x k (the reference).
+// sin theta_k(Z, U) = sqrt(lambda_max(W^T W)), W = U - Z (Z^T U); one workgroup
+// per Z (Z + blockIdx.x z_stride, result out[blockIdx.x]).  Z is d x r (the
+// iterate, r >= k columns), U is d x k (the reference).  With diff (r == k) the
+// kernel returns ||Z - U||_2 instead (W = Z - U).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
-sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
-                 const double* __restrict__ U, double* __restrict__ out,
+sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Zs, int64_t z_stride,
+                 int diff, const double* __restrict__ U, double* __restrict__ out,
                  double* __restrict__ hist, int32_t* __restrict__ ctr) {
+  const double* Z = Zs + (int64_t)blockIdx.x * z_stride;
   __shared__ double C[kMaxK * kMaxK];
   __shared__ double G[kMaxK * kMaxK];
   __shared__ double Wt[16 * kMaxK];
@@ -884,7 +887,7 @@ sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
   __shared__ int flag;
   const int kk = k * k;
   // C = Z^T U (r x k)
-  for (int e = threadIdx.x; e < r * k; e += blockDim.x) {
+  for (int e = threadIdx.x; e < (diff ? 0 : r * k); e += blockDim.x) {
     const int i = e / k, j = e - (e / k) * k;
     double s = 0.0;
     for (int64_t q = 0; q < d; ++q) s = fma(Z[q * r + i], U[q * k + j], s);
@@ -900,7 +903,11 @@ sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
       const int rr = e / k, j = e - (e / k) * k;
       const double* zr = Z + (r0 + rr) * r;
       double s = U[(r0 + rr) * k + j];
-      for (int l = 0; l < r; ++l) s = fma(-zr[l], C[l * k + j], s);
+      if (diff) {
+        s = zr[j] - s;
+      } else {
+        for (int l = 0; l < r; ++l) s = fma(-zr[l], C[l * k + j], s);
+      }
       Wt[e] = s;
     }
     __syncthreads();
@@ -927,7 +934,7 @@ sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
     double mx = 0.0;
     for (int j = 0; j < k; ++j) mx = fmax(mx, G[j * k + j]);
     const double v = sqrt(fmax(mx, 0.0));
-    if (out != nullptr) out[0] = v;
+    if (out != nullptr) out[blockIdx.x] = v;
     if (hist != nullptr) {
       hist[*ctr] = v;
       *ctr = *ctr + 1;
@@ -1038,7 +1045,33 @@ hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* l
 
 hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const double* U,
                             double* out, double* hist, int32_t* ctr, hipStream_t s) {
-  sin_theta_kernel<<<1, kBlock, 0, s>>>(d, r, k, Z, U, out, hist, ctr);
+  sin_theta_kernel<<<1, kBlock, 0, s>>>(d, r, k, Z, 0, 0, U, out, hist, ctr);
+  return hipGetLastError();
+}
+
+// rho (Definition 3) of the m local iterates Zi (m x d x k) against partition 0's:
+// per partition ||Z_i - Z_1||_2, or with OPT sin theta_max(Z_i, Z_1) turned into
+// min_O ||Z_i O - Z_1||_2 = 2 sin(theta_max / 2); the maximum is appended to
+// hist[*ctr].  m == 0 appends 0 (rounds of one local step).
+__global__ void rho_finish_kernel(int m, int opt, const double* __restrict__ part,
+                                  double* __restrict__ hist, int32_t* __restrict__ ctr) {
+  if (threadIdx.x != 0) return;
+  double v = 0.0;
+  for (int i = 0; i < m; ++i) v = fmax(v, part[i]);
+  if (opt) {
+    const double sn = fmin(v, 1.0);
+    v = sn * sqrt(2.0 / (1.0 + sqrt(fmax(0.0, 1.0 - sn * sn))));
+  }
+  hist[*ctr] = v;
+  *ctr = *ctr + 1;
+}
+
+hipError_t launch_rho(int m, int64_t d, int k, bool opt, const double* Zi, double* part,
+                      double* hist, int32_t* ctr, hipStream_t s) {
+  if (m > 0)
+    sin_theta_kernel<<<m, kBlock, 0, s>>>(d, k, k, Zi, d * k, opt ? 0 : 1, Zi, part, nullptr,
+                                          nullptr);
+  rho_finish_kernel<<<1, 64, 0, s>>>(m, opt ? 1 : 0, part, hist, ctr);
   return hipGetLastError();
 }
 

@@ -120,6 +120,9 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   L.hist = take(kHistCap * 8);
   L.ctr = take(4);
   L.scal = take(64 * 8);
+  L.rho = take(kHistCap * 8);
+  L.rho_part = take(mb * 8);
+  L.rho_ctr = take(4);
   L.total = o;
   return true;
 }
@@ -187,10 +190,10 @@ using namespace lp;
 namespace {
 
 struct Ptrs {
-  double *Zi, *Yi, *Z, *Y, *Uref, *gram, *omat, *hist;
+  double *Zi, *Yi, *Z, *Y, *Uref, *gram, *omat, *hist, *rho, *rho_part;
   void *Zw, *Zw_shared, *part, *tbuf;
   int8_t* sgn;
-  int32_t *flags, *slot_off, *ctr;
+  int32_t *flags, *slot_off, *ctr, *rho_ctr;
   WorkItem* items;
 };
 
@@ -206,6 +209,9 @@ Ptrs ptrs(lp_problem* P) {
   p.gram = (double*)(w + L.gram);
   p.omat = (double*)(w + L.omat);
   p.hist = (double*)(w + L.hist);
+  p.rho = (double*)(w + L.rho);
+  p.rho_part = (double*)(w + L.rho_part);
+  p.rho_ctr = (int32_t*)(w + L.rho_ctr);
   p.Zw = w + L.Zw;
   p.Zw_shared = w + L.Zw_shared;
   p.part = w + L.part;
@@ -399,6 +405,12 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, int hist) {
   for (int l = 1; l <= p; ++l) {
     const void* zsrc = (l == 1) ? q.Zw_shared : q.Zw;
     const int64_t zstride = (l == 1) ? 0 : dk;
+    if (l == p && p >= 2 && P->rho_now) {
+      // residual error of the inputs of the last local step (before any alignment)
+      if ((e = launch_rho(m, d, k, mode == LP_AGG_OPT, q.Zi, q.rho_part, q.rho, q.rho_ctr, s)) !=
+          hipSuccess)
+        return e;
+    }
     if (l == p && p >= 2 && mode != LP_AGG_VANILLA) {
       // align the inputs of the last local step against the base node's
       const double* Zb = q.Zi + (int64_t)P->base * dk;
@@ -426,6 +438,9 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, int hist) {
         return e;
     }
   }
+  if (p == 1 && P->rho_now &&
+      (e = launch_rho(0, d, k, false, q.Zi, q.rho_part, q.rho, q.rho_ctr, s)) != hipSuccess)
+    return e;
   if ((e = launch_aggregate_gram(m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, q.gram, s)) != hipSuccess)
     return e;
   if ((e = cholqr2_from_gram(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + m, s)) !=
@@ -446,7 +461,7 @@ lp_status run_round(lp_problem* P, int k, int p, lp_agg mode, int hist, bool use
     return LP_OK;
   }
   GraphKey key{k, p, (int)mode, hist, slot, slot >= 0 && P->timing_first_only ? 1 : 0,
-               P->split_now ? 1 : 0};
+               P->split_now ? 1 : 0, P->rho_now ? 1 : 0};
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -942,7 +957,8 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     const bool fused =
         (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, P->d, P->lda, k)) ||
         (P->plan.path == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, P->d, P->lda, k, P->A));
-    split = P->can_split && !P->gram_on && (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
+    split = P->can_split && !P->gram_on && o.rho_out == nullptr &&
+            (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
   }
   if (split && P->stream2 == nullptr) {
     // the second stream and its events exist only in problems that run split
@@ -970,6 +986,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   if ((st = join_in(P)) != LP_OK) return st;
   LP_HIP(launch_fill_i32(q.flags, m + 2, 0, s));
   LP_HIP(launch_fill_i32(q.ctr, 1, 0, s));
+  LP_HIP(launch_fill_i32(q.rho_ctr, 1, 0, s));
   if (hist) LP_HIP(hipMemcpyAsync(q.Uref, o.U_ref, (size_t)d * k_ref * 8, hipMemcpyDeviceToDevice, s));
   // Z_0 = orth(Y_0) (Algorithm 1, initialisation)
   if (o.z0_orthonormal) {
@@ -979,9 +996,10 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     LP_HIP(cholqr2(P->plan, P->ws, 1, d, k, Y0, q.Z, q.Zw_shared, q.flags + m, s));
   }
   LP_HIP(hipEventRecord(P->ev_t0, s));
-  int rounds = 0, iters = 0, hist_done = 0, graph_rounds = 0;
+  int rounds = 0, iters = 0, hist_done = 0, rho_done = 0, graph_rounds = 0;
   P->timing = timing;
   P->split_now = split;
+  P->rho_now = o.rho_out != nullptr;
   std::vector<std::pair<int, int>> pending;  // (slot, p) of timed graph rounds not yet harvested
   for (int r = 0; r < T; ++r) {
     const int p = p_sched[r];
@@ -1009,6 +1027,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     if (st != LP_OK) {
       P->timing = false;
       P->split_now = false;
+      P->rho_now = false;
       return st;
     }
     if ((int)pending.size() == kTimedSlots || (r == T - 1 && !pending.empty()))
@@ -1031,8 +1050,16 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
       LP_HIP(hipStreamSynchronize(s));
       hist_done = rounds;
     }
+    if (P->rho_now && (rounds - rho_done == kHistCap || r == T - 1)) {
+      LP_HIP(hipMemcpyAsync(o.rho_out + rho_done, q.rho, (size_t)(rounds - rho_done) * 8,
+                            hipMemcpyDeviceToHost, s));
+      LP_HIP(launch_fill_i32(q.rho_ctr, 1, 0, s));
+      LP_HIP(hipStreamSynchronize(s));
+      rho_done = rounds;
+    }
   }
   P->split_now = false;
+  P->rho_now = false;
   LP_HIP(hipEventRecord(P->ev_t1, s));
   if (timing) LP_HIP(drain_timing(P));
   P->timing = false;

@@ -32,7 +32,7 @@ enum class LocalPath : int { TwoPass = 0, Mfma32 = 1, MfmaBf16 = 2 };
 struct Layout {
   // byte offsets into the workspace
   size_t Zi, Zw, Yi, tmp, Z, Zw_shared, Y, Uref, part, tbuf, gram, gram2, rinv, omat, sgn, flags,
-      items, slot_off, hist, ctr, scal, total;
+      items, slot_off, hist, ctr, scal, rho, rho_part, rho_ctr, total;
 };
 
 constexpr int kHistCap = 1024;  // rounds of sin-theta history buffered on the device
@@ -65,7 +65,9 @@ struct GraphKey {
   int32_t k, p, mode, hist, slot;  // slot >= 0: timed instance with its own event pairs
   int32_t first_only;              // timed instance brackets only the round's first step
   int32_t split;                   // partitions in two halves on two streams
+  int32_t rho = 0;                 // the round appends its residual error (Definition 3)
   bool operator<(const GraphKey& o) const {
+    if (rho != o.rho) return rho < o.rho;
     if (k != o.k) return k < o.k;
     if (p != o.p) return p < o.p;
     if (mode != o.mode) return mode < o.mode;
@@ -76,8 +78,6 @@ struct GraphKey {
   }
 };
 
-// One half of the partitions for split rounds: partitions [b0, b0 + nb) and
-// their work items [it0, it0 + nit) (items are in partition order).
 // Truth-free stop rule with a decaying p (the serving layer and lp_solve).
 // After every round, step() takes the change c = sin theta_k(Z_r, Z_{r-1});
 // q = c / c_prev over rounds at the same p; with Q the larger of the last two
@@ -113,6 +113,8 @@ struct StopRule {
   }
 };
 
+// One half of the partitions for split rounds: partitions [b0, b0 + nb) and
+// their work items [it0, it0 + nit) (items are in partition order).
 struct Half {
   int32_t b0, nb, it0, nit;
 };
@@ -155,6 +157,7 @@ struct lp_problem {
   hipEvent_t ev_k1[2] = {nullptr, nullptr};
   bool can_split = false;   // m >= 2
   bool split_now = false;   // the rounds being enqueued are split
+  bool rho_now = false;     // the rounds being enqueued append their residual error
   lp::Half half[2];
   double* change_host = nullptr;   // pinned cell for lp_solve's per-round change
   // local-Gram form (lp_gram_enable): M_i = A_i^T A_i in a caller-owned buffer
@@ -285,6 +288,10 @@ hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const doub
                             double* out, double* hist, int32_t* ctr, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
+// rho (Definition 3) of the m local iterates Zi (m x d x k, FP64) against the
+// first partition's, appended to hist[*ctr]; part: m doubles of scratch.
+hipError_t launch_rho(int m, int64_t d, int k, bool opt, const double* Zi, double* part,
+                      double* hist, int32_t* ctr, hipStream_t s);
 
 // Read `bytes` (a multiple of 16) of `buf` once with 128-bit loads.
 hipError_t launch_stream_read(const void* buf, size_t bytes, hipStream_t s);

@@ -464,3 +464,23 @@ def test_solve_round_limit_and_arguments(lib, fp64_small):
     for p0, target, rounds in ((0, 1e-6, 10), (4, 0.0, 10), (4, 1e-6, 0)):
         with pytest.raises(lib.LPError):
             lib.lp_solve(P, w.k, "opt", w.Y0, p0, target, rounds)
+
+
+# --------------------------------------------------------------------- residual error (Definition 3)
+
+@pytest.mark.parametrize("mode", ["sign", "opt", "vanilla"])
+def test_rho_against_oracle(lib, fp64_small, mode):
+    """rho at every round's last local step (0 for p = 1 rounds), graph-replayed
+    and plain, against the oracle; the iterates are unchanged by measuring it."""
+    w, A, U, lam = fp64_small
+    _flush(f"rho {mode}")
+    sched = [4, 1, 3, 2, 4, 4]
+    P = _problem(lib, to_device(w), w.offsets, w.k)
+    r0 = lib.lp_run(P, w.k, sched, mode, w.Y0)
+    r = lib.lp_run(P, w.k, sched, mode, w.Y0, record_rho=True, split_rounds=True)
+    r2 = lib.lp_run(P, w.k, sched, mode, w.Y0, record_rho=True, use_graph=False)
+    assert torch.equal(r0["Z"], r["Z"]) and np.array_equal(r["rho"], r2["rho"])
+    assert r["stats"]["split_rounds"] == 0
+    ro = oracle.localpower(A, w.offsets, w.k, sched, mode, w.Y0)
+    assert np.abs(r["rho"] - np.array(ro["rho"])).max() < 1e-10
+    assert r["rho"][1] == 0.0 and r["rho"][0] > 0.0

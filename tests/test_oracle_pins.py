@@ -457,3 +457,43 @@ def test_eta_grows_with_m():
     A = synth.lowrank_plus_noise(4096, 32, synth.spectrum_c1(32, 4), 0.05, 11).numpy()
     e = [oracle.eta(A, synth.equal_offsets(4096, m)) for m in (2, 8, 32)]
     assert e[0] < e[1] < e[2]
+
+
+# ---------------------------------------------------------------- rho (Definition 3)
+
+def test_residual_error_opt_brute_force_and_closed_form():
+    """min over orthogonal O of ||Z_i O - Z_1||_2 (k = 2): a dense grid over all
+    rotations and reflections never beats the oracle's value, which equals
+    2 sin(theta_max / 2) of the principal angles."""
+    rng = np.random.default_rng(4)
+    for _ in range(25):
+        Z1 = _rand_orth(rng, 7, 2)
+        Zi = oracle.orth(Z1 + 0.6 * rng.standard_normal((7, 2)))
+        got = oracle.residual_error([Z1, Zi], True)
+        best = min(np.linalg.norm(Zi @ R - Z1, 2)
+                   for a in np.linspace(0, 2 * np.pi, 2001)
+                   for R in (np.array([[np.cos(a), -np.sin(a)], [np.sin(a), np.cos(a)]]),
+                             np.array([[np.cos(a), np.sin(a)], [np.sin(a), -np.cos(a)]])))
+        assert got <= best + 1e-12 and best - got < 2e-3
+        assert abs(got - 2 * np.sin(np.arcsin(oracle.sin_theta(Zi, Z1)) / 2)) < 1e-12
+    # without OPT it is the plain spectral norm of the difference: a sign flip costs 2
+    Z1 = _rand_orth(rng, 7, 3)
+    assert abs(oracle.residual_error([Z1, Z1 * np.array([1, -1, 1])], False) - 2.0) < 1e-12
+    assert oracle.residual_error([Z1, Z1 * np.array([1, -1, 1])], True) < 1e-12
+
+
+def test_residual_error_zero_at_p1_and_grows_with_p():
+    """rho is 0 when every node starts the step from the broadcast Z (p = 1), and
+    the spread of the local iterates grows with the local steps between
+    communications; OPT keeps it below the plain difference."""
+    w = synth.make_small(3000, 40, 4, 6, seed=2, noise=0.3)
+    A = w.A.numpy()
+    r1 = oracle.localpower(A, w.offsets, 4, [1] * 3, "sign", w.Y0)
+    assert max(r1["rho"]) == 0.0
+    last = {}
+    for p in (2, 4, 8):
+        ro = oracle.localpower(A, w.offsets, 4, [p] * 6, "opt", w.Y0)
+        rs = oracle.localpower(A, w.offsets, 4, [p] * 6, "sign", w.Y0)
+        assert ro["rho"][-1] <= rs["rho"][-1] + 1e-15
+        last[p] = ro["rho"][-1]
+    assert last[2] < last[4] < last[8]
