@@ -405,9 +405,16 @@ def main():
     k1_ms = ms_local / max(launches, 1)
     if gram is not None:
         # the Gram form streams the m stacked d x d FP32 matrices per local multiply
-        achieved = gram["bytes_per_launch"] / (k1_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        # (2 m d^2 k flops over 4 m d^2 bytes: k / 2 flop per byte)
+        gbs = gram["bytes_per_launch"] / (k1_ms / 1e3) / 1e9
+        if k / 2 > FP32_MATRIX_PEAK_TFS * 1e3 / HBM_PEAK_GBS:
+            tfs = 2.0 * w.m * d * d * k / (k1_ms / 1e3) / 1e12
+            roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": FP32_MATRIX_PEAK_TFS,
+                    "unit": "TFLOP/s", "frac": round(tfs / FP32_MATRIX_PEAK_TFS, 4),
+                    "hbm_gbs": round(gbs, 2)}
+        else:
+            roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)}
     elif spec["bound"] == "hbm":
         achieved = bytes_iter / (k1_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
