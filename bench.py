@@ -50,7 +50,8 @@ CSRC = os.path.join(ROOT, "paper_2002_08014_amd", "csrc")
 # counter summary file, bound of the local multiply
 WORKLOADS = {
     "fp32-262144x1024": dict(gen="make_fp32_262144x1024", sources=("k_local.hip", "k_mfma.hip"),
-                             traffic="local_multiply_traffic.json", bound="hbm"),
+                             traffic="local_multiply_traffic.json", bound="hbm",
+                             gram_traffic="local_multiply_gram_traffic.json"),
     "bf16-1048576x2048": dict(gen="make_bf16_1048576x2048", sources=("k_mfma_bf16.hip",),
                               traffic="local_multiply_bf16_traffic.json", bound="hbm"),
     "fp32-uneven-500000x4096": dict(gen="make_fp32_uneven_500000x4096", sources=("k_gemm.hip",),
@@ -424,7 +425,13 @@ def main():
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MATRIX_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MATRIX_PEAK_TFS, 4),
                 "hbm_gbs": round(bytes_iter / (k1_ms / 1e3) / 1e9, 2)}
-    roof.update({"traffic": None if gram else traffic_per_launch(spec), "kernel_ms": round(k1_ms, 5), "launches": launches,
+    if gram is None:
+        traffic = traffic_per_launch(spec)
+    elif "gram_traffic" in spec:
+        traffic = traffic_per_launch({"traffic": spec["gram_traffic"], "sources": ("k_gemm.hip",)})
+    else:
+        traffic = None
+    roof.update({"traffic": traffic, "kernel_ms": round(k1_ms, 5), "launches": launches,
                  "measured_read_gbs": round(read_gbs, 1), "measured_copy_gbs": round(copy_gbs, 1)})
     dtype = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float64: "f64"}[w.A.dtype]
     ps = sorted(set(sched), reverse=True)
