@@ -145,3 +145,28 @@ def test_eta_against_oracle(lp, m):
                             / (w.offsets[i + 1] - w.offsets[i]) - Mm, 2) / nm for i in range(m)]
     assert abs(eta - oracle.eta(A, w.offsets)) < 1e-3 * eta
     assert np.abs(per - np.array(per_o)).max() < 1e-3 * max(per_o)
+
+
+@pytest.mark.parametrize("which", ["bf16-1048576x2048", "fp32-uneven-500000x4096"])
+def test_gram_full_size_sampled_large(lp, which):
+    """The other two benchmark shapes in the Gram form (the launch configuration of
+    `bench.py --gram`): BF16 1048576 x 2048 with k = 32 over 64 partitions, and FP32
+    500000 x 4096 with k = 64 over 100 lognormal partitions; the smallest, the
+    largest and one middle partition against the FP32 bound."""
+    print(f"gram form full size {which}", flush=True)
+    w = (synth.make_bf16_1048576x2048 if which.startswith("bf16") else
+         synth.make_fp32_uneven_500000x4096)(device="cuda:0")
+    P = lp.lp_create(w.A, w.offsets, w.k)
+    lp.lp_gram_enable(P)
+    Z = oracle.orth(np.random.default_rng(13).standard_normal((w.d, w.k)))
+    Y = host(lp.lp_local_multiply(P, w.k, torch.as_tensor(Z)))
+    Zw = Z.astype(np.float32).astype(np.float64)
+    sizes = np.diff(w.offsets)
+    for i in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), w.m // 2}):
+        Ai = w.A[w.offsets[i]:w.offsets[i + 1]].to("cpu").to(torch.float64).numpy()
+        ref = Ai.T @ (Ai @ Zw)
+        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+        s = Ai.shape[0]
+        assert np.all(np.abs(Y[i] - ref) <= (s + w.d) * U_32 * (1 + s * U_32) * bound), i
+    del P, w
+    torch.cuda.empty_cache()
