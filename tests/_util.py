@@ -34,3 +34,22 @@ def to_device(w, dtype=None):
 def upcast(A_dev: torch.Tensor) -> np.ndarray:
     """Exact FP64 copy of the stored values (FP32/BF16 -> FP64 is exact)."""
     return A_dev.to("cpu").to(torch.float64).numpy()
+
+
+def rule_schedule(changes, p0, target):
+    """The stop rule as include/lp.h states it, applied to a list of changes:
+    returns the p of every round and whether the last round settled at p = 1."""
+    p, prev_c, prev_q, ps = p0, -1.0, -1.0, []
+    for c in changes:
+        ps.append(p)
+        q = c / prev_c if prev_c > 0 else -1.0
+        qe = max(q, prev_q) if (q >= 0 and prev_q >= 0) else -1.0
+        ratio = 0 <= qe < 1
+        est = c * qe / (1 - qe) if ratio else c
+        settled = c == 0 or (ratio and est <= 0.5 * target)
+        prev_q, prev_c = q, c
+        if settled and p == 1:
+            return ps, True
+        if p > 1 and (settled or q > 0.5):
+            p, prev_c, prev_q = max(1, p // 2), -1.0, -1.0
+    return ps, False

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from tests._util import host, sign_normalise, sin_theta_np, to_device, upcast
+from tests._util import host, rule_schedule, sign_normalise, sin_theta_np, to_device, upcast
 
 pytestmark = pytest.mark.gpu
 
@@ -402,25 +402,6 @@ def test_sin_theta_wider_iterate(lib):
 
 # --------------------------------------------------------------------- truth-free stop, decaying p
 
-def _rule_schedule(changes, p0, target):
-    """The stop rule as include/lp.h states it, applied to a list of changes:
-    returns the p of every round and whether the last round settled at p = 1."""
-    p, prev_c, prev_q, ps = p0, -1.0, -1.0, []
-    for c in changes:
-        ps.append(p)
-        q = c / prev_c if prev_c > 0 else -1.0
-        qe = max(q, prev_q) if (q >= 0 and prev_q >= 0) else -1.0
-        ratio = 0 <= qe < 1
-        est = c * qe / (1 - qe) if ratio else c
-        settled = c == 0 or (ratio and est <= 0.5 * target)
-        prev_q, prev_c = q, c
-        if settled and p == 1:
-            return ps, True
-        if p > 1 and (settled or q > 0.5):
-            p, prev_c, prev_q = max(1, p // 2), -1.0, -1.0
-    return ps, False
-
-
 @pytest.mark.parametrize("mode", ["sign", "opt"])
 def test_solve_against_oracle(lib, fp64_small, mode):
     """lp_solve: every round's change sin theta(Z_r, Z_{r-1}) against the oracle
@@ -442,7 +423,7 @@ def test_solve_against_oracle(lib, fp64_small, mode):
         ch.append(oracle.sin_theta(Zn, Z))
         Z = Zn
     assert np.abs(np.array(ch) - g["changes"]).max() < 1e-10
-    ps_rule, done = _rule_schedule(ch, 4, target)
+    ps_rule, done = rule_schedule(ch, 4, target)
     assert done and ps_rule == ps
     lam_o, Zr_o, _ = oracle.ritz(A, Z)
     assert np.abs(host(g["ritz"]) - lam_o).max() < 1e-10 * lam_o[0]
