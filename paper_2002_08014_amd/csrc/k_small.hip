@@ -217,6 +217,22 @@ __device__ __forceinline__ void chol_inv_wave(const double* G, double* Ri, int k
       const double v = G[min(i, k - 1) * k + min(cc, k - 1)];
       g[i] = (i < k && cc < k) ? v : (i == cc ? 1.0 : 0.0);
     }
+    // G = I + E with max |E| < 1e-8 (the second pass of CholeskyQR2 on an
+    // already orthonormal block): R = I + F + O(E^2) with F = the strict upper
+    // triangle of E plus half its diagonal, so R^{-1} = I - F + O(E^2), exact to
+    // rounding at this size of E; no pivots, square roots or substitution
+    // (a NaN entry fails the comparison and takes the full factorization, which
+    // flags it)
+    bool near = true;
+#pragma unroll
+    for (int i = 0; i < KM; ++i) near = near && fabs(g[i] - (i == cc ? 1.0 : 0.0)) < 1e-8;
+    if (__all(near)) {
+      if (c < k) {
+#pragma unroll
+        for (int i = 0; i < KM; ++i)
+          if (i < k) Ri[i * k + c] = i < c ? -g[i] : (i == c ? 1.5 - 0.5 * g[i] : 0.0);
+      }
+    } else {
     bool badw = false;
     // column-oriented elimination: step j makes row j of R (lane c: R[j][c]) and
     // updates the trailing rows; entries below the diagonal are never read
@@ -248,6 +264,7 @@ __device__ __forceinline__ void chol_inv_wave(const double* G, double* Ri, int k
         if (i < k) Ri[i * k + c] = badw ? (i == c ? 1.0 : 0.0) : g[i];
     }
     if (c == 0 && badw) *bad = 1;
+    }
   }
   __syncthreads();
 }
