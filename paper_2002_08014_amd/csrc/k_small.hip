@@ -340,7 +340,22 @@ chol_inv_blocked_kernel(int nch, int k, const double* __restrict__ gin, double* 
     R[e] = 0.0;
     X[e] = 0.0;
   }
-  __syncthreads();
+  // G = I + E with every |E_ij| < 1e-8 (the second pass of CholeskyQR2): the
+  // first-order inverse factor I - F (F = strict upper triangle of E plus half its
+  // diagonal) is exact to FP64 rounding; a NaN entry fails the test
+  int near = 1;
+  for (int e = t; e < KM * KM; e += kBlock) {
+    const int i = e / KM, j = e - (e / KM) * KM;
+    near = near && fabs(S[e] - (i == j ? 1.0 : 0.0)) < 1e-8;
+  }
+  if (__syncthreads_and(near)) {
+    for (int e = t; e < kk; e += kBlock) {
+      const int i = e / k, j = e - (e / k) * k;
+      const double g = S[i * KM + j];
+      rinv[(int64_t)b * kk + e] = i < j ? -g : (i == j ? 1.5 - 0.5 * g : 0.0);
+    }
+    return;
+  }
   for (int J = 0; J < NB; ++J) {
     const int dj = 16 * J * KM + 16 * J;
     chol16_wave(&S[dj], &R[dj], &X[dj], KM, &bad);
