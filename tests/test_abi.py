@@ -60,3 +60,25 @@ def test_workspace_size_validation_on_host():
         _lib.lp_workspace_size(torch.float32, 2000, 100, offs, 65)     # k_max > 64
     with pytest.raises(_lib.LPError):
         _lib.lp_workspace_size(torch.float32, 2000, 4, offs, 5)        # k_max > d
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblp.so not built")
+def test_abi_from_plain_c(tmp_path):
+    """The header compiles as C99 (-Wall -Wextra -pedantic, warnings are errors) and a
+    C program linked against liblp.so gets the same answers as the Python binding."""
+    import shutil
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "abi_from_c")
+    libdir = os.path.dirname(LIB)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-o", exe,
+                    os.path.join(ROOT, "tests", "host", "abi_from_c.c"), "-L" + libdir, "-llp",
+                    "-Wl,-rpath," + libdir], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    from paper_2002_08014_amd import _lib
+    st, nbytes = out[0].split()
+    assert int(st) == _lib.LP_OK
+    assert int(nbytes) == _lib.lp_workspace_size(torch.float64, 2000, 100,
+                                                 np.array([0, 500, 1000, 1500, 2000]), 5)
+    assert out[1].startswith(f"{_lib.LP_EINVAL} ") and out[2]
