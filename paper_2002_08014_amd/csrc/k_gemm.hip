@@ -50,8 +50,11 @@ __device__ inline f4 load4<__hip_bfloat16>(const __hip_bfloat16* p) {
 }
 
 // pass 1: t[row][n] = sum_c A[row][c] Z[c][n]; grid (items, ceil(max item rows / 128));
-// BK: contraction slice staged per step
-template <typename TA, int NT, int BK, int MT>
+// BK: contraction slice staged per step.  SPLIT > 1 (the local-Gram form, items of
+// equal rows): grid (items x SPLIT, ...), workgroup column s of item it sums the
+// contraction columns [s cs, (s + 1) cs) (cs = d / SPLIT rounded up to 4) into the
+// partial t + ((it.slot SPLIT + s) it.rows + row) k
+template <typename TA, int NT, int BK, int MT, int SPLIT = 1>
 __global__ void __launch_bounds__(256)
 tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ Zw,
            int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ t) {
@@ -64,12 +67,16 @@ tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
   constexpr int AE = (BM * AQ) / 256;    // 4-element groups per thread per slice
   __shared__ float As[2][BM * AP];
   __shared__ float Zs[2][BK * ZP];
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[blockIdx.x / SPLIT];
   const int64_t r0 = (int64_t)blockIdx.y * BM;
   if (r0 >= it.rows) return;
   const int rows = (int)min<int64_t>(BM, it.rows - r0);
-  const TA* Ab = A + (it.row0 + r0) * lda;
-  const float* Z = Zw + (int64_t)it.part * z_stride;
+  const int sp = (int)(blockIdx.x % SPLIT);
+  const int64_t cs = SPLIT == 1 ? d : ((d + 4 * SPLIT - 1) / (4 * SPLIT)) * 4;
+  const int64_t cb = (int64_t)sp * cs;                   // first contraction column
+  d = SPLIT == 1 ? d : min<int64_t>(cs, d - cb);          // contraction length of this block
+  const TA* Ab = A + (it.row0 + r0) * lda + cb;
+  const float* Z = Zw + (int64_t)it.part * z_stride + cb * k;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, i = lane & 15;
 
   // staging: A slice BM x BK as AE groups of 4 elements per thread (row (tid + 256 j) / AQ,
@@ -130,7 +137,7 @@ tmm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
     if (s + 1 < nsl) stash(b ^ 1);
     __syncthreads();
   }
-  float* tb = t + (it.row0 + r0) * k;
+  float* tb = t + (SPLIT == 1 ? it.row0 + r0 : ((int64_t)it.slot * SPLIT + sp) * it.rows + r0) * k;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -277,7 +284,7 @@ hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda,
 
 hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void* Zw,
                                 int64_t z_stride, void* tbuf, const WorkItem* items, int m,
-                                hipStream_t s) {
+                                int split, hipStream_t s) {
   // pass 1 alone over the stacked d x d matrices: item i covers rows i d .. i d + d - 1
   dim3 g(m, (unsigned)((P.d + kBM1 - 1) / kBM1));
   const float* Z = (const float*)Zw;
@@ -286,9 +293,16 @@ hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void
   if (k <= 16) {
     // HBM-bound at k <= 16 (8 flop per byte of M): 64-row blocks (twice the
     // workgroups) and 32-deep slices (128-byte row segments per load) stream M at
-    // 5.6 TB/s against 3.7 with the two-pass tiles (m = 32, d = 1024)
-    dim3 g1(m, (unsigned)((P.d + 63) / 64));
-    tmm_kernel<float, 1, 32, 1><<<g1, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+    // 5.6 TB/s against 3.7 with the two-pass tiles (m = 32, d = 1024); splitting
+    // the contraction in two halves (two partial Y_i per partition, summed by the
+    // reduction) doubles the workgroups again: 6.3 TB/s (24.2 -> 21.5 us)
+    if (split == 2) {
+      dim3 g2(2 * m, (unsigned)((P.d + 63) / 64));
+      tmm_kernel<float, 1, 32, 1, 2><<<g2, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+    } else {
+      dim3 g1(m, (unsigned)((P.d + 63) / 64));
+      tmm_kernel<float, 1, 32, 1><<<g1, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
+    }
   } else if (k <= 32) tmm_kernel<float, 2, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
   else if (k <= 48) tmm_kernel<float, 3, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);
   else tmm_kernel<float, 4, kBK, MT><<<g, 256, 0, s>>>(M, P.d, P.d, k, Z, z_stride, items, t);

@@ -261,6 +261,14 @@ hipError_t capture_event_node(hipStream_t s, hipEvent_t ev) {
 // One local iteration on every partition: Yi = A_i^T (A_i Z_i).  When this
 // launch is timed, it is bracketed by a pair of events: external event nodes of
 // the timed graph instance being captured, or plain event records.
+// The local-Gram form splits the contraction of its multiply in two at k <= 16
+// when the partial buffer holds two Y_i per partition; the reduction then reads
+// the matching slot offsets.
+int gram_split(const lp_problem* P, int k) { return (k <= 16 && P->gram_split2) ? 2 : 1; }
+const int32_t* gram_slots(const lp_problem* P, int k) {
+  return gram_split(P, k) == 2 ? P->gram_slot_off + P->m + 1 : P->gram_slot_off;
+}
+
 hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
   Ptrs p = ptrs(P);
   hipError_t e;
@@ -280,7 +288,7 @@ hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
   }
   if (P->gram_on)
     e = launch_gram_multiply(P->plan, P->gram_M, k, zsrc, zstride, p.tbuf, P->gram_items, P->m,
-                             P->stream);
+                             gram_split(P, k), P->stream);
   else
     e = launch_local_multiply(P->plan, P->A, P->lda, k, zsrc, zstride, p.tbuf, p.part, p.items,
                               (int)P->plan.items.size(), P->stream);
@@ -289,8 +297,8 @@ hipError_t local_iter(lp_problem* P, int k, const void* zsrc, int64_t zstride) {
     e = (P->timing_slot >= 0) ? capture_event_node(P->stream, ev1) : hipEventRecord(ev1, P->stream);
     if (e != hipSuccess) return e;
   }
-  if (P->gram_on)  // one FP32 "partial" per partition: Y_i itself
-    return launch_reduce_gram(P->plan, k, p.tbuf, P->gram_slot_off, p.Yi, p.gram, 0, P->m,
+  if (P->gram_on)  // Y_i itself, or its two contraction halves, as the FP32 partials
+    return launch_reduce_gram(P->plan, k, p.tbuf, gram_slots(P, k), p.Yi, p.gram, 0, P->m,
                               P->stream);
   return launch_reduce_gram(P->plan, k, p.part, p.slot_off, p.Yi, p.gram, 0, P->m, P->stream);
 }
@@ -1164,7 +1172,7 @@ lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, doub
 lp_status lp_gram_bytes(const lp_problem* P, size_t* bytes) {
   if (P == nullptr || bytes == nullptr) return fail(LP_EINVAL, "NULL argument");
   const size_t d = (size_t)P->d, m = (size_t)P->m;
-  *bytes = align256(m * d * d * 4) + align256(m * sizeof(WorkItem)) + align256((m + 1) * 4);
+  *bytes = align256(m * d * d * 4) + align256(m * sizeof(WorkItem)) + align256(2 * (m + 1) * 4);
   return LP_OK;
 }
 
@@ -1222,11 +1230,14 @@ lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes) {
       return fail(LP_EDEVICE, std::string("Gram product: ") + rocblas_status_to_string(rs));
   }
   std::vector<WorkItem> hi(m);
-  std::vector<int32_t> ho(m + 1);
+  std::vector<int32_t> ho(2 * (m + 1));
   for (int i = 0; i < m; ++i) hi[i] = WorkItem{i, i, (int64_t)i * d, d};
-  for (int i = 0; i <= m; ++i) ho[i] = i;
+  for (int i = 0; i <= m; ++i) {
+    ho[i] = i;
+    ho[m + 1 + i] = 2 * i;
+  }
   LP_HIP(hipMemcpyAsync(items, hi.data(), m * sizeof(WorkItem), hipMemcpyHostToDevice, P->stream));
-  LP_HIP(hipMemcpyAsync(slot_off, ho.data(), (m + 1) * 4, hipMemcpyHostToDevice, P->stream));
+  LP_HIP(hipMemcpyAsync(slot_off, ho.data(), 2 * (m + 1) * 4, hipMemcpyHostToDevice, P->stream));
   LP_HIP(hipStreamSynchronize(P->stream));
   // captured rounds launch the other form's kernels
   for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1234,6 +1245,7 @@ lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes) {
   P->gram_M = M;
   P->gram_items = items;
   P->gram_slot_off = slot_off;
+  P->gram_split2 = 2 * (int64_t)m * d <= P->n;   // the partial buffer holds n x k_max values
   P->gram_on = true;
   return join_out(P);
 }
@@ -1293,8 +1305,8 @@ lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y
   LP_HIP(launch_to_working(P->plan, 1, P->d, k, Z, q.Zw_shared, P->stream));
   if (P->gram_on) {
     LP_HIP(launch_gram_multiply(P->plan, P->gram_M, k, q.Zw_shared, 0, q.tbuf, P->gram_items, P->m,
-                                P->stream));
-    LP_HIP(launch_reduce_partials(P->plan, k, q.tbuf, P->gram_slot_off, Y_out, P->stream));
+                                gram_split(P, k), P->stream));
+    LP_HIP(launch_reduce_partials(P->plan, k, q.tbuf, gram_slots(P, k), Y_out, P->stream));
     return join_out(P);
   }
   LP_HIP(launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,

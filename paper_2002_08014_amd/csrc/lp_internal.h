@@ -130,7 +130,8 @@ struct lp_problem {
   bool gram_on = false;
   float* gram_M = nullptr;
   lp::WorkItem* gram_items = nullptr;
-  int32_t* gram_slot_off = nullptr;
+  int32_t* gram_slot_off = nullptr;   // [0..m]: i (one slot each); [m+1..2m+1]: 2 i
+  bool gram_split2 = false;           // tbuf holds two partial Y_i per partition
   void* blas = nullptr;            // rocBLAS handle for the one-time Gram products
 };
 
@@ -189,10 +190,11 @@ hipError_t launch_eta(int64_t d, int m, int64_t n, const float* Mi, const double
 int eta_start_vectors();
 // Local-Gram form: Y_i = M_i Z_i for the m stacked FP32 d x d matrices M_i = A_i^T A_i
 // (row-major, M_i at M + i d d); items[i] = {i, i, i d, d}; writes Y_i (FP32) to
-// tbuf + i d k.
+// tbuf + i d k, or with split == 2 (k <= 16 only) the two halves of the contraction
+// to tbuf + (2 i + h) d k.
 hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void* Zw,
                                 int64_t z_stride, void* tbuf, const WorkItem* items, int m,
-                                hipStream_t s);
+                                int split, hipStream_t s);
 hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                       const WorkItem* items, int nitems,
