@@ -37,11 +37,14 @@ def _check(Y, A, offsets, Zw, parts):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("d,k", [(96, 5), (260, 16), (260, 33), (1100, 64)])
-def test_gram_local_multiply(lp, d, k, dtype):
-    print(f"gram form d={d} k={k} {dtype}", flush=True)
+@pytest.mark.parametrize("d,k,rows", [(96, 5, 3), (260, 16, 3), (260, 16, 1), (260, 33, 3),
+                                      (1100, 64, 3)])
+def test_gram_local_multiply(lp, d, k, rows, dtype):
+    """rows = n / (m d): 3 lets the k <= 16 multiply split its contraction in two
+    (2 m d <= n), 1 keeps it whole."""
+    print(f"gram form d={d} k={k} n/(m d)={rows} {dtype}", flush=True)
     m = 5
-    n = 3 * m * d + 77
+    n = rows * m * d + 77
     w = synth.make_small(n, d, k, m, seed=d + k, dtype=dtype, uneven=True, device="cuda:0")
     P = lp.lp_create(w.A, w.offsets, k)
     lp.lp_gram_enable(P)
