@@ -19,7 +19,12 @@ Pins (checked by the CPU test-suite against mathematics, not against itself):
   * the rank-r iterate converges at lambda_{r+1} / lambda_k (subspace iteration);
   * eta has a closed form on axis-aligned partitions;
   * the OPT residual error equals a brute-force minimum over rotations and
-    2 sin(theta_max / 2).
+    2 sin(theta_max / 2);
+  * orth is the thin QR with a positive diagonal R (upper-triangular Q^T Y,
+    Q R = Y, equal to plain Gram-Schmidt), also where LAPACK's own R has
+    negative diagonal entries;
+  * the orthonormalised Gaussian start meets the initial-angle bound of the
+    appendix (Lemma "initial") at the stated rates.
 Qualitative behaviours (error floors growing with p, decay reaching DPI
 precision, vanilla instability) are checked as trends only: parity unpinned
 for the exact values of p > 1 runs on large workloads, which only the

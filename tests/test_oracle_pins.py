@@ -299,6 +299,94 @@ def test_orthonormal_iterates():
     assert worst[0] < 1e-14 and np.abs(Z.T @ Z - np.eye(w.k)).max() < 1e-14
 
 
+def _gram_schmidt(Y):
+    """Thin QR by modified Gram-Schmidt in plain loops: each column is the
+    remainder of y_j after removing its components along q_1..q_{j-1},
+    divided by its (positive) norm, so R_jj > 0 by construction."""
+    d, k = Y.shape
+    Q = [[float(Y[i, j]) for j in range(k)] for i in range(d)]
+    for j in range(k):
+        for i in range(j):
+            c = sum(Q[r][i] * Q[r][j] for r in range(d))
+            for r in range(d):
+                Q[r][j] -= c * Q[r][i]
+        nrm = math.sqrt(sum(Q[r][j] ** 2 for r in range(d)))
+        for r in range(d):
+            Q[r][j] /= nrm
+    return np.array(Q)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_orth_is_the_positive_diagonal_qr(seed):
+    """orth(Y) is the thin QR factor whose R has a positive diagonal (the
+    reading of the paper's unspecified QR sign convention): Q^T Q = I,
+    R = Q^T Y upper triangular with R_jj > 0, Q R = Y, and Q equals plain
+    Gram-Schmidt.  The inputs are chosen so that LAPACK's own Householder R
+    has negative diagonal entries, which orth must flip."""
+    rng = np.random.default_rng(100 + seed)
+    d, k = 40, 7
+    for _ in range(50):
+        Y = rng.standard_normal((d, k)) * rng.uniform(0.5, 2.0, k)[None, :]
+        if np.any(np.diag(np.linalg.qr(Y)[1]) < 0):
+            break
+    else:
+        pytest.fail("no input with a negative Householder diagonal")
+    Q = oracle.orth(Y)
+    R = Q.T @ Y
+    scale = np.abs(Y).max()
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-14
+    assert np.abs(np.tril(R, -1)).max() < 1e-14 * scale
+    assert np.all(np.diag(R) > 0)
+    assert np.abs(Q @ np.triu(R) - Y).max() < 1e-14 * scale
+    assert np.abs(Q - _gram_schmidt(Y)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- T14: initial angle
+
+def _tan_theta(U, Z):
+    """tan theta_k(U, Z) = ||(U_perp^T Z)(U^T Z)^+||_2 (the appendix's list of
+    facts on principal angles), U d x k orthonormal, Z d x r (r >= k)."""
+    d, k = U.shape
+    full, _ = np.linalg.qr(np.hstack([U, np.eye(d)]))
+    Uperp = full[:, k:d]
+    return float(np.linalg.norm((Uperp.T @ Z) @ np.linalg.pinv(U.T @ Z), 2))
+
+
+@pytest.mark.parametrize("r", [5, 6, 8, 16])
+def test_initial_angle_bound(r):
+    """T14, Lemma "initial" (Hardt and Price's Lemma 2.4): for a random
+    orthonormal start Z_0 (orth of the Gaussian start, as every run starts),
+    tan theta_k(U, Z_0) <= tau sqrt(d) / (sqrt(r) - sqrt(k - 1)) except with
+    probability tau^-Omega(r + 1 - k) + e^-Omega(d); tau = 10 over 200 draws.
+    With r = k the failure probability is only tau^-Omega(1): a k x k Gaussian
+    block has sigma_min below eps / sqrt(k) with probability about eps, which
+    puts the rate near 1 / (2 tau) = 5 %; with r > k no draw may fail.
+    Statistical; a degenerate start orthogonal to U violates it (tan =
+    infinity), and for r = k the tangent agrees with the principal-angle form
+    sin/cos of sigma_min(U^T Z)."""
+    d, k, tau = 200, 5, 10.0
+    rng = np.random.default_rng(r)
+    U = _rand_orth(rng, d, k)
+    bound = tau * math.sqrt(d) / (math.sqrt(r) - math.sqrt(k - 1))
+    tans = []
+    for t in range(200):
+        Z0 = oracle.orth(synth.gaussian_start(d, r, 1000 * r + t))
+        tans.append(_tan_theta(U, Z0))
+        if r == k and t < 20:
+            c = np.linalg.svd(U.T @ Z0, compute_uv=False).min()
+            assert abs(tans[-1] - math.sqrt(1 - c * c) / c) < 1e-9 * max(1.0, tans[-1])
+    fails = float(np.mean(np.array(tans) > bound))
+    if r == k:
+        assert fails <= 0.12
+    else:
+        assert fails == 0.0
+    # more columns than the target rank shrink the angle (the r in the bound)
+    assert np.median(tans) < bound / 5
+    # a start orthogonal to U has no component to amplify: the bound fails
+    basis, _ = np.linalg.qr(np.hstack([U, rng.standard_normal((d, r))]))
+    assert not (_tan_theta(U, basis[:, k:k + r]) <= bound)
+
+
 # ---------------------------------------------------------------- T11-T13: trends
 
 def test_floor_grows_with_p_and_decay_reaches_dpi():
