@@ -1,0 +1,209 @@
+"""Whole-run parity at the configured sizes against the FP64 oracle on the host.
+
+Every run follows Algorithm 1 for its full schedule on the GPU (through the C
+ABI, in the launch configuration the benchmark times) and once more in the
+oracle (NumPy FP64 on exact upcasts of the stored values):
+
+* 262144 x 1024 FP32, k = 16, m = 32: T = 50 rounds of p = 4 with sign-fixing
+  and with OPT, and p decaying 4 -> 2 -> 1 (10, 10, 30 rounds); subspace
+  within 1e-5, sign decisions bit-equal every round, Ritz values within 1e-5;
+* 1048576 x 2048, k = 32, m = 64, p = 8, 4, 2, 1 for 10 rounds each, OPT:
+  BF16 storage on the fused BF16-operand kernel within 2e-2 of the oracle on
+  the BF16 values and of the oracle on the original FP64 matrix; BF16 storage
+  with FP32 operands within 1e-5 of the oracle on the BF16 values; FP32
+  storage within 1e-5 of the oracle on the original matrix (its storage error
+  alone is about 1e-7);
+* 500000 x 4096 FP32, k = 64, m = 100 lognormal partitions, p = 4, T = 30,
+  OPT: within 1e-5.
+
+Ritz vectors are compared entrywise after a sign normalisation, within the
+subspace tolerance times (1 + lambda_1 / gap_j), gap_j the distance of Ritz
+value j to the others: a subspace rotated by the tolerance moves a vector by
+that much, and perturbs H = Z^T M Z by about tolerance * lambda_1, which moves
+eigenvector j by at most that over its gap.
+Each oracle run is made once per module and shared by the assertions.
+"""
+
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._util import host, sign_normalise, sin_theta_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lp(gpu_lib):
+    import paper_2002_08014_amd as lp
+    return lp
+
+
+def _host64(A_dev):
+    """Exact FP64 host copy of the stored values (FP32/BF16 -> FP64 is exact),
+    converted on the device and copied in row blocks."""
+    n, d = A_dev.shape
+    out = np.empty((n, d), dtype=np.float64)
+    step = max(1, (1 << 28) // d)
+    for r0 in range(0, n, step):
+        out[r0:r0 + step] = A_dev[r0:r0 + step].to(torch.float64).cpu().numpy()
+    return out
+
+
+def _oracle_run(A, w, sched, mode, label):
+    """The oracle over the whole schedule, one round per call (each round
+    starts from the previous round's Z, exactly as inside one call), so that
+    progress can be printed between rounds."""
+    t0 = time.perf_counter()
+    Z, signs, ambiguous, last = None, [], 0, time.perf_counter()
+    for j, p in enumerate(sched):
+        r = oracle.localpower(A, w.offsets, w.k, [p], mode, w.Y0, Z_init=Z)
+        Z = r["Z"]
+        signs += r["signs"]
+        ambiguous += r["ambiguous"]
+        if time.perf_counter() - last > 30:
+            last = time.perf_counter()
+            _say(f"oracle {label}: round {j + 1} of {len(sched)}, {last - t0:.0f} s")
+    r = {"Z": Z, "signs": signs, "ambiguous": ambiguous}
+    lam, Zr, _ = oracle.ritz(A, Z)
+    r["ritz"], r["Zritz"] = lam, Zr
+    _say(f"oracle {label}: {time.perf_counter() - t0:.1f} s ({sum(sched)} local iterations)")
+    return r
+
+
+def _gpu_run(lp, P, w, sched, mode, label, signs=False):
+    t0 = time.perf_counter()
+    r = lp.lp_run(P, w.k, sched, mode, w.Y0, ritz=True, record_signs=signs)
+    torch.cuda.synchronize()
+    _say(f"gpu {label}: {time.perf_counter() - t0:.2f} s")
+    return r
+
+
+def _compare(r, ro, tol, label):
+    """Subspace, Ritz values and Ritz vectors of a GPU run against an oracle run."""
+    Zg = host(r["Z"])
+    s = sin_theta_np(Zg, ro["Z"])
+    lam_o = ro["ritz"]
+    lam_g = host(r["ritz"])
+    rel = float(np.max(np.abs(lam_g - lam_o) / np.abs(lam_o)))
+    gaps = np.array([min(abs(lam_o[j] - lam_o[i]) for i in range(len(lam_o)) if i != j)
+                     for j in range(len(lam_o))])
+    dz = np.abs(sign_normalise(Zg) - sign_normalise(ro["Zritz"])).max(axis=0)
+    _say(f"{label}: sin theta {s:.3e}, Ritz rel {rel:.3e}, worst vector ratio "
+         f"{float(np.max(dz * gaps / lam_o[0])):.3e} (tolerance {tol:.0e})")
+    assert s <= tol, (label, s)
+    assert rel <= tol, (label, rel)
+    assert np.all(dz <= tol * (1.0 + lam_o[0] / gaps)), (label, dz, gaps)
+
+
+# ------------------------------------------------------------ 262144 x 1024 FP32
+
+C2_RUNS = {
+    "sign_T50": ([4] * 50, "sign"),
+    "opt_T50": ([4] * 50, "opt"),
+    "decay_4_2_1": ([4] * 10 + [2] * 10 + [1] * 30, "sign"),
+}
+
+
+@pytest.fixture(scope="module")
+def c2(lp):
+    _say("generating 262144 x 1024 FP32 (seed 1)")
+    w = synth.make_fp32_262144x1024(device="cuda:0")
+    A = _host64(w.A)
+    P = lp.lp_create(w.A, w.offsets, w.k)
+    lp.lp_autotune(P, w.k)           # the benchmark's tuning step
+    return w, A, P, {}
+
+
+@pytest.mark.parametrize("name", sorted(C2_RUNS))
+def test_fp32_262144x1024_whole_run(lp, c2, name):
+    w, A, P, cache = c2
+    sched, mode = C2_RUNS[name]
+    r = _gpu_run(lp, P, w, sched, mode, f"262144x1024 {name}", signs=True)
+    ro = _oracle_run(A, w, sched, mode, f"262144x1024 {name}")
+    _compare(r, ro, 1e-5, f"262144x1024 {name}")
+    assert r["stats"]["breakdowns"] == 0 and r["stats"]["near_singular"] == 0
+    if mode == "sign":
+        assert ro["ambiguous"] == 0
+        exp = np.stack([s if s is not None else np.zeros((w.m, w.k), np.int8) for s in ro["signs"]])
+        assert np.array_equal(r["signs"], exp)
+
+
+# ------------------------------------------------------------ 1048576 x 2048 precision form
+
+@pytest.fixture(scope="module")
+def c3(lp):
+    _say("generating 1048576 x 2048 in FP64 (seed 2); BF16 and FP32 stores by one rounding")
+    w = synth.make_bf16_1048576x2048(device="cuda:0", dtype=torch.float64)
+    A64_dev = w.A
+    stores = {"bf16": A64_dev.to(torch.bfloat16), "fp32": A64_dev.to(torch.float32)}
+    torch.cuda.synchronize()
+    sched, mode = list(w.p_sched), w.mode
+    assert mode == "opt" and sched == [8] * 10 + [4] * 10 + [2] * 10 + [1] * 10
+    out = {"w": w, "sched": sched, "mode": mode, "gpu": {}}
+    # GPU runs first (the device copies are freed before the host oracle runs)
+    P = lp.lp_create(stores["bf16"], w.offsets, w.k)
+    lp.lp_autotune(P, w.k)
+    out["gpu"]["bf16_bf16_operands"] = _gpu_run(lp, P, w, sched, mode, "bf16 storage, bf16 operands")
+    lp.lp_set_tuning(P, 1)
+    out["gpu"]["bf16_fp32_operands"] = _gpu_run(lp, P, w, sched, mode, "bf16 storage, fp32 operands")
+    lp.lp_destroy(P)
+    P = lp.lp_create(stores["fp32"], w.offsets, w.k)
+    lp.lp_autotune(P, w.k)
+    out["gpu"]["fp32"] = _gpu_run(lp, P, w, sched, mode, "fp32 storage")
+    lp.lp_destroy(P)
+    _say("copying the BF16 values and the original matrix to the host")
+    A_bf = _host64(stores["bf16"])
+    del stores
+    A_64 = A64_dev.cpu().numpy()
+    w.A = None
+    del A64_dev
+    torch.cuda.empty_cache()
+    out["oracle_bf16_values"] = _oracle_run(A_bf, w, sched, mode, "1048576x2048 on the BF16 values")
+    del A_bf
+    out["oracle_original"] = _oracle_run(A_64, w, sched, mode, "1048576x2048 on the original FP64 A")
+    del A_64
+    return out
+
+
+def test_bf16_storage_bf16_operands(c3):
+    r = c3["gpu"]["bf16_bf16_operands"]
+    _compare(r, c3["oracle_bf16_values"], 2e-2, "bf16 storage, bf16 operands vs oracle on the bf16 values")
+    _compare(r, c3["oracle_original"], 2e-2, "bf16 storage, bf16 operands vs oracle on the original A")
+
+
+def test_bf16_storage_fp32_operands(c3):
+    r = c3["gpu"]["bf16_fp32_operands"]
+    _compare(r, c3["oracle_bf16_values"], 1e-5, "bf16 storage, fp32 operands vs oracle on the bf16 values")
+    _compare(r, c3["oracle_original"], 2e-2, "bf16 storage, fp32 operands vs oracle on the original A")
+
+
+def test_fp32_storage(c3):
+    _compare(c3["gpu"]["fp32"], c3["oracle_original"], 1e-5, "fp32 storage vs oracle on the original A")
+
+
+# ------------------------------------------------------------ 500000 x 4096 uneven partitions
+
+def test_fp32_uneven_500000x4096_whole_run(lp):
+    _say("generating 500000 x 4096 FP32 with lognormal partitions (seed 3)")
+    w = synth.make_fp32_uneven_500000x4096(device="cuda:0")
+    assert w.mode == "opt" and list(w.p_sched) == [4] * 30 and w.m == 100
+    P = lp.lp_create(w.A, w.offsets, w.k)
+    lp.lp_autotune(P, w.k)
+    r = _gpu_run(lp, P, w, list(w.p_sched), w.mode, "500000x4096 opt")
+    assert r["stats"]["split_rounds"] == 1          # the benchmark's launch configuration
+    lp.lp_destroy(P)
+    A = _host64(w.A)
+    w.A = None
+    torch.cuda.empty_cache()
+    ro = _oracle_run(A, w, list(w.p_sched), w.mode, "500000x4096 opt")
+    _compare(r, ro, 1e-5, "500000x4096 opt")
+    assert r["stats"]["breakdowns"] == 0 and r["stats"]["near_singular"] == 0
