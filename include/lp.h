@@ -20,8 +20,13 @@
  *     pointers are CPU memory.  Matrices are row-major with the stated leading
  *     dimension; d x k matrices are dense (leading dimension k).
  *   - Inputs are BORROWED (the caller keeps them alive while in use); outputs
- *     are caller-owned.  The library allocates no device memory: all scratch
- *     lives in the workspace the caller passes to lp_create.
+ *     are caller-owned.  Problems allocate no device memory: their scratch
+ *     lives in the workspace the caller passes to lp_create (and, for the
+ *     local-Gram form and eta, in the buffer passed to lp_gram_enable);
+ *     lp_sin_theta uses one of 64 result cells the library holds in static
+ *     device memory.  The serving layer (lp_server_*) is the exception: it
+ *     allocates each admitted job's footprint with stream-ordered allocation
+ *     (hipMallocAsync) and frees it when the job ends, and pinned host cells.
  *   - All GPU work is enqueued on the stream given to lp_create (a hipStream_t;
  *     NULL means the legacy default stream); calls that return host results
  *     synchronise that stream before returning.
@@ -110,13 +115,20 @@ lp_status lp_destroy(lp_problem* P);
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
  *                 default chosen at lp_create, which sized the workspace); 0 = default.
  *   cached_loads: 1 reads A with ordinary (cached) loads in the fused kernels; 0 (default)
- *                 with nontemporal loads, since A is streamed once per local iteration. */
+ *                 with nontemporal loads, since A is streamed once per local iteration.
+ *   split_operands: BF16 A only.  0 (default): the fused BF16 kernel rounds Z and
+ *                 t = A Z once to BF16 (a sin theta floor near 1e-3 against FP64 on the
+ *                 same values, within the BF16 tolerance of 2e-2).  1: each operand is a
+ *                 pair hi = bf16(x), lo = bf16(x - hi) and every product is taken twice,
+ *                 FP32-class results for twice the matrix-core work; at k = 32, d = 2048
+ *                 (the pairs do not fit a CU's registers) the two-pass kernel with FP32
+ *                 operands runs instead.  The autotuner keeps this setting. */
 typedef struct {
   int32_t struct_size;
   int32_t local_kernel;
   int64_t chunk_rows;
   int32_t cached_loads;
-  int32_t reserved;
+  int32_t split_operands;
 } lp_tuning;
 
 /* Apply a tuning to a problem (host-side; re-uploads the work list on the problem's
@@ -172,6 +184,12 @@ typedef struct {
                             max_i ||Z_i - Z_1||_2, or with OPT max_i min_O ||Z_i O - Z_1||_2
                             = 2 sin(theta_max(Z_i, Z_1) / 2); 0 for rounds with p = 1.
                             Rounds then run on one stream. */
+  uint64_t seed;         /* with Y0 == NULL: the Gaussian start is drawn from this seed
+                            (Philox4x32-10, element e = i k + j of the d x k start from
+                            counter (e mod 2^32, e / 2^32, 0, 0x5a300001) under key (seed
+                            mod 2^32, seed / 2^32); Box-Muller, cosine branch, of the
+                            uniforms (w0 / 2^5 * 2^26 + w1 / 2^6 + 1) / 2^53 and likewise
+                            from w2, w3) */
 } lp_run_opts;
 
 typedef struct {
@@ -198,7 +216,8 @@ typedef struct {
  *             a decaying schedule, or p = T total for one-shot); COPIED.
  *   mode    : alignment used when p_sched[r] >= 2 (rounds with p = 1 use none).
  *   Y0      : device d x k FP64 start matrix (the Gaussian Y_0 of Algorithm 1);
- *             Z_0 = orth(Y0) unless opts->z0_orthonormal.
+ *             Z_0 = orth(Y0) unless opts->z0_orthonormal.  NULL: Y_0 is drawn on the
+ *             device from opts->seed (seed 0 without opts) and Z_0 = orth(Y_0).
  *   Z_out   : device d x k FP64, receives Z_T = orth(aggregate of the last round).
  *   ritz_out: device [k] FP64 or NULL: when given, one extra p = 1 pass forms
  *             H = Z^T M Z, Z_out is rotated to its eigenvectors and ritz_out gets the
@@ -220,6 +239,9 @@ typedef struct {
   int32_t z0_orthonormal;  /* as in lp_run_opts */
   int32_t* p_used;         /* host [max_rounds] or NULL: p of every round run */
   double* change_out;      /* host [max_rounds] or NULL: c_r of every round run */
+  uint64_t seed;           /* with Y0 == NULL: seed of the Gaussian start, as in
+                              lp_run_opts (a struct_size that stops before this field
+                              means seed 0) */
 } lp_solve_opts;
 
 typedef struct {
@@ -251,8 +273,9 @@ lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, doub
 /* ---------------------------------------------------------------------------
  * Local-Gram form of the local multiply.  Eq. (power_yi) costs O(d^2 k) per local
  * iteration with M_i formed and O(s_i d k) without it.  lp_gram_enable computes M_i' = A_i^T A_i
- * (d x d, FP32, one dense GEMM per partition through rocBLAS, on the problem's
- * stream) into a caller-owned device buffer of lp_gram_bytes bytes; from then on
+ * (d x d, FP32 accumulation of exact products, one launch on the FP32 matrix cores over
+ * all partitions, on the problem's stream) into a caller-owned device buffer of
+ * lp_gram_bytes bytes (which also holds the scratch of lp_eta); from then on
  * every local multiply of the problem (lp_run, lp_solve, lp_local_multiply, the
  * Ritz pass) computes Y_i = M_i' Z_i on the FP32 matrix cores, reading m d^2
  * FP32 values instead of n d values of A.  It pays when m d is well below n (the
@@ -275,8 +298,9 @@ lp_status lp_gram_disable(lp_problem* P);
  * spectral norm is estimated by `iters` steps of power iteration from four fixed
  * pseudo-random start vectors (an estimate from below that converges at the rate
  * (lambda_2 / lambda_1)^2 per step).  eta_out: host double; per_part_out: host [m]
- * ||M_i - M||_2 / ||M||_2, or NULL.  Allocates and frees device scratch of about
- * 8 d^2 + 64 (m + 1) d bytes and synchronises the stream. */
+ * ||M_i - M||_2 / ||M||_2, or NULL.  Its scratch (about 8 d^2 + 64 (m + 1) d bytes) is
+ * part of the buffer given to lp_gram_enable; allocates nothing; synchronises the
+ * problem's stream. */
 lp_status lp_eta(lp_problem* P, int32_t iters, double* eta_out, double* per_part_out);
 
 /* One local power iteration on every partition with a shared Z (the worker step
@@ -317,9 +341,32 @@ lp_status lp_bandwidth_probe(const void* buf, size_t bytes, int32_t iters, doubl
 lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters, double* gbs_out,
                         void* stream);
 
+/* Exact-truth test matrix (not part of the paper: a synthetic input whose top-k
+ * subspace is known without an eigendecomposition, used by the serving layer to
+ * generate jobs on the device).  A = W diag(sigma) V^T with
+ *   W (n x d): n / d Sylvester-Hadamard blocks (entries +-1, W^T W = n I), rows
+ *     permuted and sign-flipped, columns sign-flipped per block;
+ *   V: a permutation matrix (a keyed permutation of the d columns);
+ *   sigma_j = 1/(j+1) for j < k, sigma_{k-1}/gap at j = k, then times decay per
+ *     index, each rounded to FP32 and then to BF16;
+ * so A^T A = n V diag(sigma^2) V^T exactly, every entry +-sigma_j is exact in FP32
+ * and BF16, and the top-k right singular vectors are V's columns for j < k.  All
+ * random choices come from Philox4x32-10 under `seed` (Salmon et al., SC 2011).
+ *   A     : device n x d, FP32 or BF16 (dtype), leading dimension lda (lda >= d,
+ *           lda % 4 == 0, A aligned to 4 elements), or NULL;
+ *   U_out : device d x k FP64 (U[c][j] = 1 where column c holds sigma_j), or NULL;
+ *   shapes: d a power of two in [16, 8192], n a positive multiple of d, 1 <= k <= d,
+ *           gap >= 1, 0 < decay <= 1.
+ * Enqueued on `stream`; asynchronous.  LP_EINVAL for other shapes. */
+lp_status lp_generate(void* A, lp_dtype dtype, int64_t n, int64_t d, int64_t lda, int32_t k,
+                      double gap, double decay, uint64_t seed, double* U_out, void* stream);
+
 /* sin theta_k(Z, U) = ||U - Z (Z^T U)||_2 (Definition 1), for device d x k FP64
- * matrices with orthonormal columns.  Uses its own small scratch on the stream
- * (no workspace), synchronises and writes the result to *out_host. */
+ * matrices with orthonormal columns.  The result goes through one of 64 device
+ * cells held by the library (taken under a lock for the duration of the call, so
+ * calls from different threads on different streams do not share one); the call
+ * synchronises `stream` and writes the result to *out_host.  LP_EBUSY when 64
+ * calls are already in flight. */
 lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
                        void* stream);
 
@@ -360,9 +407,11 @@ lp_status lp_sin_theta_r(const double* Z, int32_t r, const double* U, int32_t k,
 typedef struct lp_server lp_server; /* opaque */
 
 typedef struct {
-  int32_t struct_size;     /* sizeof(lp_job) */
+  int32_t struct_size;     /* sizeof(lp_job); a size that stops before `stream` means
+                              stream NULL and no generation (the fields below it) */
   const void* A;           /* device n x d row-major (leading dimension lda, 16-byte
-                              aligned rows), BORROWED until the job's result is polled */
+                              aligned rows), BORROWED until the job's result is polled;
+                              NULL: generated at admission (see gen_seed) */
   lp_dtype dtype;
   int64_t n, d, lda;
   const int64_t* offsets;  /* host, m + 1 entries as for lp_create; COPIED at submit */
@@ -372,8 +421,26 @@ typedef struct {
   lp_agg mode;
   double target;           /* > 0 */
   int32_t max_rounds;      /* >= 1 */
-  const double* Y0;        /* host d x k FP64 start, COPIED at submit; orthonormalised */
+  const double* Y0;        /* host d x k FP64 start, COPIED at submit; orthonormalised;
+                              NULL: drawn on the device from gen_seed as lp_run draws it
+                              from lp_run_opts.seed */
   double* Z_out;           /* device d x k FP64, caller-owned, written when the job ends */
+  void* stream;            /* hipStream_t on which the caller writes A and uses Z_out
+                              (NULL: the legacy default stream).  lp_server_submit records
+                              an event on it; the job waits for that event before its
+                              first GPU work, so work queued there before the submit (A
+                              being written, Z_out's memory still being read) comes first.
+                              Z_out is complete when the job's result is polled. */
+  uint64_t gen_seed;       /* seed of the generated A and/or start */
+  double gen_gap, gen_decay; /* A == NULL: the job's A is lp_generate(dtype, n, d, lda = d,
+                              k, gen_gap, gen_decay, gen_seed) written at admission into
+                              the job's own device memory (part of its footprint), so
+                              only admitted jobs hold a matrix; needs the shapes
+                              lp_generate takes */
+  int32_t single_bf16;     /* BF16 A: 0 (default) the job's local multiplies use
+                              FP32-class operands (split_operands of lp_tuning), since
+                              its stop rule aims at a sin theta target; 1 one BF16
+                              rounding of Z and t (faster; a floor near 1e-3) */
 } lp_job;
 
 typedef struct {
@@ -389,7 +456,8 @@ typedef struct {
 } lp_job_result;
 
 /* Device bytes the server allocates for `job` (its lp_workspace_size plus the
- * start, previous-iterate and change buffers); A and Z_out are the caller's. */
+ * start, previous-iterate and change buffers, plus n d b bytes for A when the
+ * job generates it); otherwise A and Z_out are the caller's. */
 lp_status lp_server_footprint(const lp_job* job, size_t* bytes);
 
 /* Create a server on the current HIP device with a device-memory budget and at

@@ -27,6 +27,7 @@ from ._lib import (  # noqa: F401
     lp_orth,
     lp_align,
     lp_sin_theta,
+    lp_generate,
     lp_bandwidth_probe,
     lp_copy_probe,
 )

@@ -25,7 +25,7 @@ MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_gram_bytes",
            "lp_gram_enable", "lp_gram_disable", "lp_eta", "lp_local_multiply", "lp_orth", "lp_align",
-           "lp_sin_theta", "lp_sin_theta_r", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
+           "lp_sin_theta", "lp_sin_theta_r", "lp_generate", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
            "lp_server_destroy")
 
@@ -41,7 +41,7 @@ class Tuning(ctypes.Structure):
                 ("local_kernel", ctypes.c_int32),
                 ("chunk_rows", ctypes.c_int64),
                 ("cached_loads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("split_operands", ctypes.c_int32)]
 
 
 class RunOpts(ctypes.Structure):
@@ -54,7 +54,8 @@ class RunOpts(ctypes.Structure):
                 ("time_local", ctypes.c_int32),
                 ("split_rounds", ctypes.c_int32),
                 ("k_ref", ctypes.c_int32),
-                ("rho_out", ctypes.POINTER(ctypes.c_double))]
+                ("rho_out", ctypes.POINTER(ctypes.c_double)),
+                ("seed", ctypes.c_uint64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -64,7 +65,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32),
                 ("z0_orthonormal", ctypes.c_int32),
                 ("p_used", ctypes.POINTER(ctypes.c_int32)),
-                ("change_out", ctypes.POINTER(ctypes.c_double))]
+                ("change_out", ctypes.POINTER(ctypes.c_double)),
+                ("seed", ctypes.c_uint64)]
 
 
 class SolveStats(ctypes.Structure):
@@ -106,7 +108,12 @@ class Job(ctypes.Structure):
                 ("target", ctypes.c_double),
                 ("max_rounds", ctypes.c_int32),
                 ("Y0", ctypes.c_void_p),
-                ("Z_out", ctypes.c_void_p)]
+                ("Z_out", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p),
+                ("gen_seed", ctypes.c_uint64),
+                ("gen_gap", ctypes.c_double),
+                ("gen_decay", ctypes.c_double),
+                ("single_bf16", ctypes.c_int32)]
 
 
 class JobResult(ctypes.Structure):
@@ -175,6 +182,9 @@ def load() -> ctypes.CDLL:
     L.lp_copy_probe.argtypes = [vp, vp, sz, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_sin_theta.restype = i32
     L.lp_sin_theta.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.lp_generate.restype = i32
+    L.lp_generate.argtypes = [vp, i32, i64, i64, i64, i32, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_uint64, vp, vp]
     L.lp_sin_theta_r.restype = i32
     L.lp_sin_theta_r.argtypes = [vp, i32, vp, i32, i64, ctypes.POINTER(ctypes.c_double), vp]
     L.lp_server_footprint.restype = i32
@@ -315,8 +325,9 @@ def lp_destroy(P: Problem) -> None:
 
 
 def lp_set_tuning(P: Problem, local_kernel: int = 0, chunk_rows: int = 0,
-                  cached_loads: bool = False) -> None:
-    t = Tuning(ctypes.sizeof(Tuning), local_kernel, chunk_rows, 1 if cached_loads else 0, 0)
+                  cached_loads: bool = False, split_operands: bool = False) -> None:
+    t = Tuning(ctypes.sizeof(Tuning), local_kernel, chunk_rows, 1 if cached_loads else 0,
+               1 if split_operands else 0)
     _check(load().lp_set_tuning(P.handle, ctypes.byref(t)), "lp_set_tuning")
 
 
@@ -324,7 +335,7 @@ def lp_get_tuning(P: Problem) -> dict:
     t = Tuning()
     _check(load().lp_get_tuning(P.handle, ctypes.byref(t)), "lp_get_tuning")
     return {"local_kernel": t.local_kernel, "chunk_rows": t.chunk_rows,
-            "cached_loads": bool(t.cached_loads)}
+            "cached_loads": bool(t.cached_loads), "split_operands": bool(t.split_operands)}
 
 
 def lp_autotune(P: Problem, k: int, cache_path: Optional[str] = None) -> dict:
@@ -333,25 +344,26 @@ def lp_autotune(P: Problem, k: int, cache_path: Optional[str] = None) -> dict:
     _check(load().lp_autotune(P.handle, k, cache_path.encode() if cache_path else None,
                               ctypes.byref(t)), "lp_autotune")
     return {"local_kernel": t.local_kernel, "chunk_rows": t.chunk_rows,
-            "cached_loads": bool(t.cached_loads)}
+            "cached_loads": bool(t.cached_loads), "split_operands": bool(t.split_operands)}
 
 
 def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool = False,
            U_ref: Optional[torch.Tensor] = None, record_signs: bool = False,
            z0_orthonormal: bool = False, use_graph: bool = True, time_local: int = 0,
-           split_rounds: Optional[bool] = None, record_rho: bool = False):
+           split_rounds: Optional[bool] = None, record_rho: bool = False, seed: int = 0):
     """Returns dict(Z, ritz, sin_hist, signs, stats); Z is a device d x k float64 tensor.
     time_local: 0 no events, 1 (or True) every local multiply timed, 2 the first
     one of every round only.  split_rounds: partitions in two halves on two streams
     (None: the library decides, True: always, False: never).  k is the iteration
     rank; U_ref may have fewer columns (the target rank), and sin_hist then holds
     sin theta of the rank-k iterate against it.  record_rho: the residual error of
-    Definition 3 at every round's last local step (rho)."""
+    Definition 3 at every round's last local step (rho).  Y0 None: the library draws
+    the Gaussian start from `seed`."""
     L = load()
     dev = P.A.device
     sched = np.ascontiguousarray(np.asarray(p_sched, dtype=np.int32))
     T = len(sched)
-    Y0d = _dev_f64(Y0, dev)
+    Y0d = None if Y0 is None else _dev_f64(Y0, dev)
     Z = torch.empty(P.d, k, dtype=torch.float64, device=dev)
     rz = torch.empty(k, dtype=torch.float64, device=dev) if ritz else None
     opts = RunOpts()
@@ -360,6 +372,7 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
     opts.use_graph = 1 if use_graph else 0
     opts.time_local = int(time_local)
     opts.split_rounds = 0 if split_rounds is None else (1 if split_rounds else 2)
+    opts.seed = int(seed)
     hist = None
     if U_ref is not None:
         Ud = _dev_f64(U_ref, dev)
@@ -385,14 +398,14 @@ def lp_run(P: Problem, k: int, p_sched: Sequence[int], mode: str, Y0, ritz: bool
 
 
 def lp_solve(P: Problem, k: int, mode: str, Y0, p0: int, target: float, max_rounds: int,
-             ritz: bool = False, z0_orthonormal: bool = False):
+             ritz: bool = False, z0_orthonormal: bool = False, seed: int = 0):
     """LocalPower with the truth-free stop rule and a decaying p (lp_solve).
     Returns dict(Z, ritz, p_used, changes, stats, status); status is LP_OK when the
     iterates settled at p = 1 and LP_ENOTCONV when max_rounds ran out (Z is then
     the last iterate); other failures raise LPError."""
     L = load()
     dev = P.A.device
-    Y0d = _dev_f64(Y0, dev)
+    Y0d = None if Y0 is None else _dev_f64(Y0, dev)
     Z = torch.empty(P.d, k, dtype=torch.float64, device=dev)
     rz = torch.empty(k, dtype=torch.float64, device=dev) if ritz else None
     p_used = np.zeros(max_rounds, dtype=np.int32)
@@ -403,6 +416,7 @@ def lp_solve(P: Problem, k: int, mode: str, Y0, p0: int, target: float, max_roun
     o.z0_orthonormal = 1 if z0_orthonormal else 0
     o.p_used = p_used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     o.change_out = changes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    o.seed = int(seed)
     st = SolveStats()
     status = L.lp_solve(P.handle, k, MODES[mode], _ptr(Y0d), _ptr(Z), _ptr(rz), ctypes.byref(o),
                         ctypes.byref(st))
@@ -465,6 +479,20 @@ def lp_sin_theta(Z: torch.Tensor, U: torch.Tensor, stream: Optional[torch.cuda.S
     return float(out.value)
 
 
+def lp_generate(n: int, d: int, k: int, gap: float, decay: float, seed: int,
+                dtype: Optional[torch.dtype] = torch.float32, basis: bool = True,
+                device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
+    """The exact-truth matrix (n x d of `dtype`, or None when dtype is None) and its
+    top-k right singular vectors (d x k float64 device, or None); lp_generate."""
+    L = load()
+    A = torch.empty(n, d, dtype=dtype, device=device) if dtype is not None else None
+    U = torch.empty(d, k, dtype=torch.float64, device=device) if basis else None
+    _check(L.lp_generate(_ptr(A), DTYPES[dtype] if dtype is not None else 1, n, d, d, k,
+                         float(gap), float(decay), int(seed), _ptr(U), _stream_handle(stream)),
+           "lp_generate")
+    return A, U
+
+
 def lp_bandwidth_probe(buf: torch.Tensor, iters: int = 5,
                        stream: Optional[torch.cuda.Stream] = None) -> float:
     """Best-of-`iters` read bandwidth (GB/s) over the bytes of a device tensor."""
@@ -504,34 +532,53 @@ class Server:
         self._jobs = {}
 
     @staticmethod
-    def _job(A: torch.Tensor, offsets: Sequence[int], k: int, p0: int, mode: str, target: float,
-             max_rounds: int, Y0, Z_out: Optional[torch.Tensor]):
-        if A.dim() != 2 or A.stride(1) != 1:
-            raise ValueError("A must be a 2-D tensor with contiguous rows")
-        if not A.is_cuda:
-            raise ValueError("A must be a device tensor")
+    def _job(A: Optional[torch.Tensor], offsets: Sequence[int], k: int, p0: int, mode: str,
+             target: float, max_rounds: int, Y0, Z_out: Optional[torch.Tensor],
+             stream: Optional[torch.cuda.Stream] = None, gen=None, single_bf16: bool = False):
+        """gen = (n, d, dtype, seed, gap, decay) when A is None (generated at admission);
+        Y0 None draws the start from the generation seed (gen[3], or 0)."""
         offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
-        y0 = np.ascontiguousarray(np.asarray(Y0, dtype=np.float64))
-        n, d = A.shape
-        if y0.shape != (d, k):
-            raise ValueError("Y0 must be d x k")
-        Z = Z_out if Z_out is not None else torch.empty(d, k, dtype=torch.float64, device=A.device)
-        job = Job(ctypes.sizeof(Job), A.data_ptr(), DTYPES[A.dtype], n, d, A.stride(0),
+        if A is not None:
+            if A.dim() != 2 or A.stride(1) != 1:
+                raise ValueError("A must be a 2-D tensor with contiguous rows")
+            if not A.is_cuda:
+                raise ValueError("A must be a device tensor")
+            n, d = A.shape
+            dt, lda, dev = DTYPES[A.dtype], A.stride(0), A.device
+            seed, gap, decay = (int(gen[3]), float(gen[4]), float(gen[5])) if gen else (0, 1.0, 1.0)
+        else:
+            n, d, dtype, seed, gap, decay = gen
+            dt, lda, dev = DTYPES[dtype], d, torch.device("cuda", torch.cuda.current_device())
+        y0 = None
+        if Y0 is not None:
+            y0 = np.ascontiguousarray(np.asarray(Y0, dtype=np.float64))
+            if y0.shape != (d, k):
+                raise ValueError("Y0 must be d x k")
+        Z = Z_out if Z_out is not None else torch.empty(d, k, dtype=torch.float64, device=dev)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        job = Job(ctypes.sizeof(Job), None if A is None else A.data_ptr(), dt, n, d, lda,
                   offs.ctypes.data, len(offs) - 1, k, p0, MODES[mode], float(target), int(max_rounds),
-                  y0.ctypes.data, Z.data_ptr())
+                  None if y0 is None else y0.ctypes.data, Z.data_ptr(), st.cuda_stream,
+                  int(seed), float(gap), float(decay), 1 if single_bf16 else 0)
         return job, (A, offs, y0, Z)
 
     @staticmethod
-    def footprint(A: torch.Tensor, offsets: Sequence[int], k: int) -> int:
-        job, keep = Server._job(A, offsets, k, 1, "sign", 1e-4, 1, np.zeros((A.shape[1], k)), None)
+    def footprint(A: Optional[torch.Tensor], offsets: Sequence[int], k: int, gen=None) -> int:
+        d = A.shape[1] if A is not None else gen[1]
+        job, keep = Server._job(A, offsets, k, 1, "sign", 1e-4, 1, np.zeros((d, k)), None, gen=gen)
         out = ctypes.c_size_t()
         _check(load().lp_server_footprint(ctypes.byref(job), ctypes.byref(out)), "lp_server_footprint")
         return out.value
 
-    def submit(self, A: torch.Tensor, offsets: Sequence[int], k: int, Y0, p0: int = 4,
+    def submit(self, A: Optional[torch.Tensor], offsets: Sequence[int], k: int, Y0, p0: int = 4,
                mode: str = "sign", target: float = 1e-4, max_rounds: int = 200,
-               Z_out: Optional[torch.Tensor] = None) -> int:
-        job, keep = self._job(A, offsets, k, p0, mode, target, max_rounds, Y0, Z_out)
+               Z_out: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None,
+               gen=None, single_bf16: bool = False) -> int:
+        """Queue a job.  A None: gen = (n, d, dtype, seed, gap, decay) describes the
+        exact-truth matrix the server generates at admission (lp_generate).  The job
+        waits for the work queued on `stream` (default: the current stream) first."""
+        job, keep = self._job(A, offsets, k, p0, mode, target, max_rounds, Y0, Z_out, stream, gen,
+                              single_bf16)
         jid = ctypes.c_uint64()
         _check(load().lp_server_submit(self.handle, ctypes.byref(job), ctypes.byref(jid)),
                "lp_server_submit")

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblp.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["lp_api.hip", "lp_server.hip", "k_local.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_gemm.hip", "k_small.hip", "k_probe.hip", "k_diag.hip"]
+SOURCES = ["lp_api.hip", "lp_server.hip", "k_local.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_gemm.hip", "k_small.hip", "k_probe.hip", "k_diag.hip", "k_gen.hip"]
 ARCH = "gfx950"
 
 
@@ -56,9 +56,7 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    # rocBLAS: only the one-time Gram products of the local-Gram form (lp_gram_enable)
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + \
-        ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

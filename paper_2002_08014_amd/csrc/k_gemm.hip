@@ -241,6 +241,101 @@ ymm_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float*
       }
 }
 
+// Gram products of the local-Gram form: M_i[c][n] = sum over the rows of
+// partition i of A[row][c] A[row][n] (M_i' = A_i^T A_i, FP32 accumulation of
+// exact products).  The same tiling as pass 2, with the second operand read
+// from A itself: workgroup (i, cb, nb) owns columns [256 cb, 256 cb + 256) of
+// rows [64 nb, 64 nb + 64) of M_i (M is symmetric, so rows and columns are
+// interchangeable) and streams the partition's rows 16 at a time.
+template <typename TA>
+__global__ void __launch_bounds__(256)
+gram_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, const WorkItem* __restrict__ parts,
+            float* __restrict__ M) {
+  constexpr int NT = 4, N = 64, BK = kBK, MT = 4;
+  constexpr int BM = 64 * MT;
+  constexpr int AP = BM + 16;
+  constexpr int AQ = BM / 4;
+  constexpr int TP = pad16(N);
+  constexpr int TE = (BK * N) / 256;
+  constexpr int AE = (BK * AQ) / 256;
+  __shared__ float As[2][BK * AP];
+  __shared__ float Ts[2][BK * TP];
+  const WorkItem it = parts[blockIdx.x];
+  const int64_t c0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.z * N;
+  const int64_t rows = it.rows;
+  const TA* Ab = A + it.row0 * lda;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, i = lane & 15;
+
+  f4 pa[AE];
+  float pt[TE];
+  auto fetch = [&](int64_t rs) {
+#pragma unroll
+    for (int j = 0; j < AE; ++j) {
+      const int64_t r = rs + (tid + 256 * j) / AQ;
+      const int64_t c = c0 + 4 * (tid % AQ);
+      pa[j] = (r < rows && c < d) ? load4<TA>(Ab + r * lda + c) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < TE; ++j) {
+      const int e = tid + 256 * j;
+      const int64_t r = rs + e / N;
+      const int64_t n = n0 + e % N;
+      pt[j] = (r < rows && n < d) ? (float)Ab[r * lda + n] : 0.f;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < AE; ++j) *(f4*)&As[b][((tid + 256 * j) / AQ) * AP + 4 * (tid % AQ)] = pa[j];
+#pragma unroll
+    for (int j = 0; j < TE; ++j) {
+      const int e = tid + 256 * j;
+      Ts[b][(e / N) * TP + e % N] = pt[j];
+    }
+  };
+
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nsl = (rows + BK - 1) / BK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int64_t s = 0; s < nsl; ++s) {
+    const int b = (int)(s & 1);
+    if (s + 1 < nsl) fetch((s + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      float a[MT], y[NT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) a[mt] = As[b][(4 * kk + g) * AP + 16 * MT * w + 16 * mt + i];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) y[nt] = Ts[b][(4 * kk + g) * TP + 16 * nt + i];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], y[nt], acc[mt][nt], 0, 0, 0);
+    }
+    if (s + 1 < nsl) stash(b ^ 1);
+    __syncthreads();
+  }
+  float* o = M + (int64_t)it.part * d * d;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t c = c0 + 16 * MT * w + 16 * mt + 4 * g + r;
+        const int64_t n = n0 + 16 * nt + i;
+        if (c < d && n < d) o[c * d + n] = acc[mt][nt][r];
+      }
+}
+
 template <typename TA, int NT>
 hipError_t gemm_pair(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
                      int64_t z_stride, void* tbuf, void* part, const WorkItem* items, int nitems,
@@ -280,6 +375,16 @@ hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda,
   if (P.dtype == LP_F32)
     return gemm_k<float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
   return gemm_k<__hip_bfloat16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+}
+
+hipError_t launch_gram_products(const Plan& P, const void* A, int64_t lda, const WorkItem* parts,
+                                int m, float* M, hipStream_t s) {
+  dim3 g(m, (unsigned)((P.d + 255) / 256), (unsigned)((P.d + 63) / 64));
+  if (P.dtype == LP_F32)
+    gram_kernel<float><<<g, 256, 0, s>>>((const float*)A, lda, P.d, parts, M);
+  else
+    gram_kernel<__hip_bfloat16><<<g, 256, 0, s>>>((const __hip_bfloat16*)A, lda, P.d, parts, M);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void* Zw,

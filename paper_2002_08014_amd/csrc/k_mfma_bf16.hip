@@ -6,6 +6,10 @@
 // reading every element of A once from HBM.  Both products run on BF16
 // matrix-core instructions with FP32 accumulation; Z_i and the intermediate
 // t = A_rows Z_i are rounded to BF16 (round to nearest even) as operands.
+// With SPLIT each operand is a pair hi = bf16(x), lo = bf16(x - hi) and every
+// product is taken twice (A hi + A lo; A is exact in BF16), so the operands
+// carry about 16 significant bits instead of 8: twice the matrix-core work for
+// FP32-class results (the single rounding leaves a sin theta floor near 1e-3).
 //
 // Layout: W waves (4 or 8), wave w owns the column slice [w*d/W, (w+1)*d/W) of
 // every 16-row tile; NC = d/(32 W) 32-column chunks per slice.
@@ -104,7 +108,7 @@ __device__ inline void wait_vm_n() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N)
 // blocks (k = 16 KT); AUX: cache policy of the A loads (0 default, 2 nontemporal);
 // AHEAD: two tiles in flight per wave (a buffer is refilled with the tile two
 // ahead as soon as this wave's last read of it is done) instead of one.
-template <int W, int NC, int KT, int AUX, bool AHEAD>
+template <int W, int NC, int KT, int AUX, bool AHEAD, bool SPLIT>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
              int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
@@ -118,7 +122,7 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
   static_assert(NC % 4 == 0 && TB % 1024 == 0, "slice must be a whole number of 256-byte groups");
   __shared__ __attribute__((aligned(16))) unsigned char abuf[2][W][TB];
   __shared__ f4 tpart[W][KT][64];
-  __shared__ __attribute__((aligned(16))) uint16_t tbf[K * kRows];   // t^T, k-major
+  __shared__ __attribute__((aligned(16))) uint16_t tbf[SPLIT ? 2 : 1][K * kRows];   // t^T, k-major
 
   const WorkItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
@@ -151,13 +155,17 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
   // Z_i slice in B-operand layout: zb[c][kt][e] = Z[slice0 + 32c + 8g + e][16kt + i]
   const float* Z = Zw + (int64_t)it.part * z_stride;
   bf8 zb[NC][KT];
+  bf8 zl[SPLIT ? NC : 1][KT];   // the low parts (SPLIT)
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        zb[c][kt][e] = (__bf16)Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * K + 16 * kt + i];
+      for (int e = 0; e < 8; ++e) {
+        const float z = Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * K + 16 * kt + i];
+        zb[c][kt][e] = (__bf16)z;
+        if constexpr (SPLIT) zl[c][kt][e] = (__bf16)(z - (float)zb[c][kt][e]);
+      }
 
   f4 yacc[NCT][KT];
 #pragma unroll
@@ -206,9 +214,15 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-          tacc[kt][c & 1] =
-              __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[c], zb[c0 + c][kt], tacc[kt][c & 1], 0, 0, 0);
+        for (int kt = 0; kt < KT; ++kt) {
+          if constexpr (SPLIT) {
+            tacc[kt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[c], zb[c0 + c][kt], tacc[kt][0], 0, 0, 0);
+            tacc[kt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[c], zl[c0 + c][kt], tacc[kt][1], 0, 0, 0);
+          } else {
+            tacc[kt][c & 1] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[c], zb[c0 + c][kt], tacc[kt][c & 1], 0, 0, 0);
+          }
+        }
     }
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) tpart[w][kt][lane] = tacc[kt][0] + tacc[kt][1];
@@ -225,14 +239,23 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
       for (int v = 1; v < W; ++v) s += tpart[v][kt][lane][r];
       const int row = 4 * g + r;
-      tbf[(i + 16 * kt) * kRows + row] = bf16_bits(row < valid ? s : 0.f);
+      const float tv = row < valid ? s : 0.f;
+      const uint16_t hb = bf16_bits(tv);
+      tbf[0][(i + 16 * kt) * kRows + row] = hb;
+      if constexpr (SPLIT) {
+        const float hi = __uint_as_float((uint32_t)hb << 16);
+        tbf[SPLIT ? 1 : 0][(i + 16 * kt) * kRows + row] = bf16_bits(tv - hi);
+      }
     }
     lds_barrier();
 
     // product 2: Y_slice += A_tile^T t
-    s4 tb_op[KT];
+    s4 tb_op[KT], tl_op[SPLIT ? KT : 1];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) tb_op[kt] = *(const s4*)&tbf[(i + 16 * kt) * kRows + 4 * g];
+    for (int kt = 0; kt < KT; ++kt) {
+      tb_op[kt] = *(const s4*)&tbf[0][(i + 16 * kt) * kRows + 4 * g];
+      if constexpr (SPLIT) tl_op[kt] = *(const s4*)&tbf[SPLIT ? 1 : 0][(i + 16 * kt) * kRows + 4 * g];
+    }
 #pragma unroll
     for (int c0 = 0; c0 < NCT; c0 += 8) {
       s4 a2[8];
@@ -244,9 +267,13 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
       for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
+        for (int kt = 0; kt < KT; ++kt) {
           yacc[c0 + c][kt] =
               __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[c], tb_op[kt], yacc[c0 + c][kt], 0, 0, 0);
+          if constexpr (SPLIT)
+            yacc[c0 + c][kt] =
+                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[c], tl_op[kt], yacc[c0 + c][kt], 0, 0, 0);
+        }
     }
     if constexpr (AHEAD) {
       // this wave's reads of buffer b are done (the asm reads wait inside)
@@ -264,49 +291,56 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
         o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * K + 16 * kt + i] = yacc[ct][kt][r];
 }
 
-template <int W, int NC, int KT, bool AHEAD>
+template <int W, int NC, int KT, bool AHEAD, bool SPLIT>
 hipError_t launch_nc(int nitems, bool nt, const uint16_t* a, int64_t lda, const float* z,
                      int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
   if (nt)
-    k1_mfma_bf16<W, NC, KT, 2, AHEAD><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_bf16<W, NC, KT, 2, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
   else
-    k1_mfma_bf16<W, NC, KT, 0, AHEAD><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_bf16<W, NC, KT, 0, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
   return hipGetLastError();
 }
 
-template <int KT, bool AHEAD>
+template <int KT, bool AHEAD, bool SPLIT>
 hipError_t launch_kt_ahead(int64_t d, bool w8, int nitems, bool nt, const uint16_t* a, int64_t lda,
                            const float* z, int64_t z_stride, const WorkItem* items, float* o,
                            hipStream_t s) {
-  if (w8 && d == 1024) return launch_nc<8, 4, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
-  if (w8 && d == 2048) return launch_nc<8, 8, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  if (w8 && d == 1024) return launch_nc<8, 4, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  if constexpr (!(SPLIT && KT == 2)) {
+    if (w8 && d == 2048) return launch_nc<8, 8, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  }
   switch (d) {
-    case 512: return launch_nc<4, 4, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 1024: return launch_nc<4, 8, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 1536: return launch_nc<4, 12, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 2048: return launch_nc<4, 16, KT, AHEAD>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 512: return launch_nc<4, 4, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 1024: return launch_nc<4, 8, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 1536: return launch_nc<4, 12, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 2048:
+      // split operands at k = 32 need 2 (Z) + 1 (Y) x 256 registers per lane over the
+      // slice of a 2048-wide row: more than one CU holds (the launcher's caller
+      // routes that case to the two-pass kernel)
+      if constexpr (SPLIT && KT == 2) return hipErrorInvalidValue;
+      else return launch_nc<4, 16, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // variant 0: four waves (any eligible d); 1: eight waves (d = 1024 or 2048);
 // 2, 3: the same with two tiles in flight per wave
-template <int KT>
+template <int KT, bool SPLIT>
 hipError_t launch_kt(int64_t d, int variant, int nitems, bool nt, const uint16_t* a, int64_t lda,
                      const float* z, int64_t z_stride, const WorkItem* items, float* o,
                      hipStream_t s) {
   const bool w8 = variant == 1 || variant == 3;
   if (variant >= 2)
-    return launch_kt_ahead<KT, true>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
-  return launch_kt_ahead<KT, false>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
+    return launch_kt_ahead<KT, true, SPLIT>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
+  return launch_kt_ahead<KT, false, SPLIT>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
 }
 
 }  // namespace
 
-bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A) {
+bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A, bool split) {
   return dtype == LP_BF16 && (k == 16 || k == 32) &&
          (d == 512 || d == 1024 || d == 1536 || d == 2048) && (lda % 8) == 0 &&
-         ((uintptr_t)A % 16) == 0;
+         ((uintptr_t)A % 16) == 0 && !(split && k == 32 && d == 2048);
 }
 
 hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
@@ -316,8 +350,12 @@ hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t ld
   const uint16_t* a = (const uint16_t*)A;
   const float* z = (const float*)Zw;
   float* o = (float*)part;
-  if (k == 32) return launch_kt<2>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
-  return launch_kt<1>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+  if (P.split_operands) {
+    if (k == 32) return launch_kt<2, true>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+    return launch_kt<1, true>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+  }
+  if (k == 32) return launch_kt<2, false>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+  return launch_kt<1, false>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
 }
 
 }  // namespace lp

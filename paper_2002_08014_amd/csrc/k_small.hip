@@ -983,11 +983,13 @@ inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
-// One-double result slot of lp_sin_theta (per device; concurrent calls race).
-__device__ double g_sin_slot[1];
+// Result cells of lp_sin_theta: one per call in flight (each GPU holds its own
+// copy of the array; a call takes a free cell under a host lock and hands it
+// back after it has synchronised, so concurrent callers never share a cell).
+__device__ double g_sin_slots[kSinSlots];
 
 hipError_t sin_slot_address(double** p) {
-  return hipGetSymbolAddress((void**)p, HIP_SYMBOL(g_sin_slot));
+  return hipGetSymbolAddress((void**)p, HIP_SYMBOL(g_sin_slots));
 }
 
 // ---------------------------------------------------------------------------

@@ -1,14 +1,13 @@
 // C ABI of the LocalPower library: problem handle, workspace layout, the
 // round driver (Algorithm 1 with sign-fixing / OPT alignment) and its hipGraph
 // replay.  Host code only; the kernels live in k_local.hip and k_small.hip.
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -33,6 +32,26 @@ lp_status fail(lp_status s, const std::string& msg) {
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Free list of the sin theta result cells (shared by all devices: a cell index
+// in use on one device is not handed out on another, which is only cautious).
+std::mutex g_sin_mu;
+uint64_t g_sin_busy = 0;
+
+int take_sin_cell() {
+  std::lock_guard<std::mutex> g(g_sin_mu);
+  for (int c = 0; c < lp::kSinSlots; ++c)
+    if (!(g_sin_busy >> c & 1)) {
+      g_sin_busy |= uint64_t(1) << c;
+      return c;
+    }
+  return -1;
+}
+
+void give_sin_cell(int c) {
+  std::lock_guard<std::mutex> g(g_sin_mu);
+  g_sin_busy &= ~(uint64_t(1) << c);
+}
 
 size_t elem_bytes(lp_dtype t) { return t == LP_F64 ? 8 : (t == LP_F32 ? 4 : 2); }
 
@@ -88,6 +107,7 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   P->min_chunk_rows = cr;
   P->variant = 1;
   P->nt_loads = true;
+  P->split_operands = false;
   build_items(P, offsets, cr);
   P->n_gram_chunks = (int32_t)((d + kGramRows - 1) / kGramRows);
   const size_t dk = (size_t)d * k_max;
@@ -149,7 +169,7 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
   if (nitems < 1) return hipSuccess;
   if (P.path == LocalPath::Mfma32 && mfma32_eligible(P.dtype, P.d, lda, k))
     return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
-  if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A))
+  if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A, P.split_operands))
     return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (gemm_eligible(P.dtype, P.d, lda, A))
     return launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
@@ -518,7 +538,7 @@ hipError_t harvest_slots(lp_problem* P, std::vector<std::pair<int, int>>& pendin
 // The fused kernel family this problem can use (TwoPass when none applies).
 LocalPath fused_kind(const lp_problem* P) {
   if (P->k_max >= 16 && mfma32_eligible(P->dtype, P->d, P->lda, 16)) return LocalPath::Mfma32;
-  if (P->k_max >= 16 && mfma16_eligible(P->dtype, P->d, P->lda, 16, P->A)) return LocalPath::MfmaBf16;
+  if (P->k_max >= 16 && mfma16_eligible(P->dtype, P->d, P->lda, 16, P->A, false)) return LocalPath::MfmaBf16;
   return LocalPath::TwoPass;
 }
 
@@ -526,7 +546,8 @@ LocalPath fused_kind(const lp_problem* P) {
 bool fused_for_k(const lp_problem* P, int k) {
   switch (fused_kind(P)) {
     case LocalPath::Mfma32: return mfma32_eligible(P->dtype, P->d, P->lda, k);
-    case LocalPath::MfmaBf16: return mfma16_eligible(P->dtype, P->d, P->lda, k, P->A);
+    case LocalPath::MfmaBf16:
+      return mfma16_eligible(P->dtype, P->d, P->lda, k, P->A, P->plan.split_operands);
     default: return false;
   }
 }
@@ -616,6 +637,12 @@ const double* drive_z(lp_problem* P) { return ptrs(P).Z; }
 lp_status report(lp_status s, const std::string& msg) { return fail(s, msg); }
 
 hipStream_t drive_stream(lp_problem* P) { return P->stream; }
+
+void drive_split_operands(lp_problem* P, bool split) {
+  P->plan.split_operands = split;
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  P->graphs.clear();
+}
 
 lp_status drive_breakdowns(lp_problem* P, int* breakdowns) {
   Ptrs q = ptrs(P);
@@ -741,7 +768,6 @@ lp_status lp_destroy(lp_problem* P) {
   if (P->ev_t0) (void)hipEventDestroy(P->ev_t0);
   if (P->ev_t1) (void)hipEventDestroy(P->ev_t1);
   if (P->change_host) (void)hipHostFree(P->change_host);
-  if (P->blas) (void)rocblas_destroy_handle((rocblas_handle)P->blas);
   delete P;
   return LP_OK;
 }
@@ -774,6 +800,7 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
     P->plan.variant = (ahead ? 2 : 0) + (eight ? 1 : 0);
   }
   P->plan.nt_loads = t->cached_loads == 0;
+  P->plan.split_operands = t->split_operands != 0;
   build_items(&P->plan, P->offsets.data(), cr);
   return upload_items(P);
 }
@@ -784,7 +811,7 @@ lp_status lp_get_tuning(lp_problem* P, lp_tuning* t) {
   t->local_kernel = P->plan.path == LocalPath::TwoPass ? 1 : 2 + P->plan.variant;
   t->chunk_rows = P->plan.chunk_rows;
   t->cached_loads = P->plan.nt_loads ? 0 : 1;
-  t->reserved = 0;
+  t->split_operands = P->plan.split_operands ? 1 : 0;
   return LP_OK;
 }
 
@@ -798,11 +825,11 @@ std::string tune_key(lp_problem* P, int k) {
   if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
   std::ostringstream os;
   os << arch << "|" << (int)P->dtype << "|" << P->n << "|" << P->d << "|" << P->m << "|" << k << "|"
-     << P->lda;
+     << P->lda << "|" << (P->plan.split_operands ? 1 : 0);
   return os.str();
 }
 
-bool cache_lookup(const std::string& path, const std::string& key, lp_tuning* t) {
+bool cache_lookup(const std::string& path, const std::string& key, int32_t split, lp_tuning* t) {
   std::ifstream f(path);
   if (!f) return false;
   std::string line;
@@ -817,7 +844,7 @@ bool cache_lookup(const std::string& path, const std::string& key, lp_tuning* t)
       t->local_kernel = lk;
       t->chunk_rows = cr;
       t->cached_loads = cached;
-      t->reserved = 0;
+      t->split_operands = split;
       found = true;
     }
   }
@@ -862,11 +889,12 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
   lp_tuning best;
   std::memset(&best, 0, sizeof(best));
   best.struct_size = sizeof(lp_tuning);
-  if (!path.empty() && cache_lookup(path, key, &best)) {
+  if (!path.empty() && cache_lookup(path, key, P->plan.split_operands ? 1 : 0, &best)) {
     if ((st = lp_set_tuning(P, &best)) != LP_OK) return st;
     if (chosen) *chosen = best;
     return LP_OK;
   }
+  const int32_t split = P->plan.split_operands ? 1 : 0;   // kept: a choice of accuracy
   const bool fused_ok = fused_for_k(P, k);
   const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 10 : 5;
   std::vector<lp_tuning> cand;
@@ -874,9 +902,9 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
     if (fused_ok) {
       for (int lk = 2; lk <= lk_max; ++lk)
-        for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, 0});
+        for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, split});
     } else {
-      cand.push_back({(int32_t)sizeof(lp_tuning), 1, cr, 0, 0});
+      cand.push_back({(int32_t)sizeof(lp_tuning), 1, cr, 0, split});
     }
   }
   if ((st = join_in(P)) != LP_OK) return st;
@@ -945,7 +973,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
     if (p_sched[r] < 1) return fail(LP_EINVAL, "every p_sched[r] must be >= 1");
   if (mode != LP_AGG_VANILLA && mode != LP_AGG_SIGN && mode != LP_AGG_OPT)
     return fail(LP_EINVAL, "unknown aggregation mode");
-  if (Y0 == nullptr || Z_out == nullptr) return fail(LP_EINVAL, "Y0 and Z_out are required");
+  if (Z_out == nullptr) return fail(LP_EINVAL, "Z_out is required");
   lp_run_opts o;
   std::memset(&o, 0, sizeof(o));
   o.use_graph = 1;
@@ -964,7 +992,8 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   {
     const bool fused =
         (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, P->d, P->lda, k)) ||
-        (P->plan.path == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, P->d, P->lda, k, P->A));
+        (P->plan.path == LocalPath::MfmaBf16 &&
+         mfma16_eligible(P->dtype, P->d, P->lda, k, P->A, P->plan.split_operands));
     split = P->can_split && !P->gram_on && o.rho_out == nullptr &&
             (o.split_rounds == 1 || (o.split_rounds == 0 && !fused));
   }
@@ -996,7 +1025,13 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   LP_HIP(launch_fill_i32(q.ctr, 1, 0, s));
   LP_HIP(launch_fill_i32(q.rho_ctr, 1, 0, s));
   if (hist) LP_HIP(hipMemcpyAsync(q.Uref, o.U_ref, (size_t)d * k_ref * 8, hipMemcpyDeviceToDevice, s));
-  // Z_0 = orth(Y_0) (Algorithm 1, initialisation)
+  // Z_0 = orth(Y_0) (Algorithm 1, initialisation); without Y0 the Gaussian
+  // start is drawn from the seed into the (still unused) local-product buffer
+  if (Y0 == nullptr) {
+    if (o.z0_orthonormal) return fail(LP_EINVAL, "z0_orthonormal needs a Y0");
+    LP_HIP(launch_gaussian(dk, o.seed, q.Yi, s));
+    Y0 = q.Yi;
+  }
   if (o.z0_orthonormal) {
     LP_HIP(hipMemcpyAsync(q.Z, Y0, dk * 8, hipMemcpyDeviceToDevice, s));
     LP_HIP(launch_to_working(P->plan, 1, d, k, q.Z, q.Zw_shared, s));
@@ -1098,15 +1133,18 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
 
 lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, double* Z_out,
                    double* ritz_out, const lp_solve_opts* opts, lp_solve_stats* stats) {
-  if (P == nullptr || Y0 == nullptr || Z_out == nullptr || opts == nullptr)
-    return fail(LP_EINVAL, "problem, Y0, Z_out and opts are required");
-  if (opts->struct_size < (int32_t)sizeof(lp_solve_opts))
+  if (P == nullptr || Z_out == nullptr || opts == nullptr)
+    return fail(LP_EINVAL, "problem, Z_out and opts are required");
+  // callers built before the seed field existed pass the shorter struct
+  if (opts->struct_size < (int32_t)offsetof(lp_solve_opts, seed))
     return fail(LP_EINVAL, "opts->struct_size too small");
+  lp_solve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  std::memcpy(&o, opts, std::min<size_t>(sizeof(o), (size_t)opts->struct_size));
   lp_status st = check_k(P, k);
   if (st != LP_OK) return st;
   if (mode != LP_AGG_VANILLA && mode != LP_AGG_SIGN && mode != LP_AGG_OPT)
     return fail(LP_EINVAL, "unknown aggregation mode");
-  const lp_solve_opts& o = *opts;
   if (o.p0 < 1 || !(o.target > 0.0) || o.max_rounds < 1)
     return fail(LP_EINVAL, "need p0 >= 1, target > 0 and max_rounds >= 1");
   if (P->change_host == nullptr) LP_HIP(hipHostMalloc((void**)&P->change_host, sizeof(double)));
@@ -1114,6 +1152,12 @@ lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, doub
   const int m = P->m;
   const int64_t dk = P->d * k;
   hipStream_t s = P->stream;
+  if (Y0 == nullptr) {
+    if (o.z0_orthonormal) return fail(LP_EINVAL, "z0_orthonormal needs a Y0");
+    if ((st = join_in(P)) != LP_OK) return st;
+    LP_HIP(launch_gaussian(dk, o.seed, q.Yi, s));
+    Y0 = q.Yi;
+  }
   if ((st = drive_begin(P, k, Y0, o.z0_orthonormal != 0)) != LP_OK) return st;
   // the previous iterate lives in the reference buffer (no reference here); the
   // change of a round goes to the first history cell
@@ -1172,7 +1216,8 @@ lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, doub
 lp_status lp_gram_bytes(const lp_problem* P, size_t* bytes) {
   if (P == nullptr || bytes == nullptr) return fail(LP_EINVAL, "NULL argument");
   const size_t d = (size_t)P->d, m = (size_t)P->m;
-  *bytes = align256(m * d * d * 4) + align256(m * sizeof(WorkItem)) + align256(2 * (m + 1) * 4);
+  *bytes = align256(m * d * d * 4) + align256(m * sizeof(WorkItem)) + align256(2 * (m + 1) * 4) +
+           align256(eta_scratch_bytes(P->d, P->m));
   return LP_OK;
 }
 
@@ -1193,42 +1238,16 @@ lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes) {
   float* M = (float*)b;
   WorkItem* items = (WorkItem*)(b + align256((size_t)m * d * d * 4));
   int32_t* slot_off = (int32_t*)((char*)items + align256((size_t)m * sizeof(WorkItem)));
-  if (P->blas == nullptr) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success)
-      return fail(LP_EDEVICE, "rocblas_create_handle failed");
-    P->blas = h;
-  }
-  rocblas_handle h = (rocblas_handle)P->blas;
-  if (rocblas_set_stream(h, P->stream) != rocblas_status_success)
-    return fail(LP_EDEVICE, "rocblas_set_stream failed");
+  char* eta = (char*)slot_off + align256(2 * (size_t)(m + 1) * 4);
   lp_status st;
   if ((st = join_in(P)) != LP_OK) return st;
-  // M_i = A_i^T A_i: the row-major s_i x d block A_i is the column-major d x s_i
-  // matrix X = A_i^T (leading dimension lda), and M_i = X X^T (symmetric, so its
-  // row- and column-major forms agree)
-  const float one = 1.f, zero = 0.f;
-  for (int i = 0; i < m; ++i) {
-    const int64_t s_i = P->offsets[i + 1] - P->offsets[i];
-    float* Mi = M + (size_t)i * d * d;
-    rocblas_status rs;
-    if (P->dtype == LP_F32) {
-      const float* X = (const float*)P->A + P->offsets[i] * P->lda;
-      rs = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)d,
-                         (rocblas_int)d, (rocblas_int)s_i, &one, X, (rocblas_int)P->lda, X,
-                         (rocblas_int)P->lda, &zero, Mi, (rocblas_int)d);
-    } else {
-      const __hip_bfloat16* X = (const __hip_bfloat16*)P->A + P->offsets[i] * P->lda;
-      rs = rocblas_gemm_ex(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)d,
-                           (rocblas_int)d, (rocblas_int)s_i, &one, X, rocblas_datatype_bf16_r,
-                           (rocblas_int)P->lda, X, rocblas_datatype_bf16_r, (rocblas_int)P->lda,
-                           &zero, Mi, rocblas_datatype_f32_r, (rocblas_int)d, Mi,
-                           rocblas_datatype_f32_r, (rocblas_int)d, rocblas_datatype_f32_r,
-                           rocblas_gemm_algo_standard, 0, 0);
-    }
-    if (rs != rocblas_status_success)
-      return fail(LP_EDEVICE, std::string("Gram product: ") + rocblas_status_to_string(rs));
-  }
+  // M_i = A_i^T A_i on the FP32 matrix cores: the work list first holds the
+  // partitions' row ranges for the Gram products, then the multiply's items
+  std::vector<WorkItem> parts(m);
+  for (int i = 0; i < m; ++i)
+    parts[i] = WorkItem{i, i, P->offsets[i], P->offsets[i + 1] - P->offsets[i]};
+  LP_HIP(hipMemcpyAsync(items, parts.data(), m * sizeof(WorkItem), hipMemcpyHostToDevice, P->stream));
+  LP_HIP(launch_gram_products(P->plan, P->A, P->lda, items, m, M, P->stream));
   std::vector<WorkItem> hi(m);
   std::vector<int32_t> ho(2 * (m + 1));
   for (int i = 0; i < m; ++i) hi[i] = WorkItem{i, i, (int64_t)i * d, d};
@@ -1245,6 +1264,7 @@ lp_status lp_gram_enable(lp_problem* P, void* buffer, size_t bytes) {
   P->gram_M = M;
   P->gram_items = items;
   P->gram_slot_off = slot_off;
+  P->gram_eta = eta;
   P->gram_split2 = 2 * (int64_t)m * d <= P->n;   // the partial buffer holds n x k_max values
   P->gram_on = true;
   return join_out(P);
@@ -1260,6 +1280,7 @@ lp_status lp_gram_disable(lp_problem* P) {
   P->gram_M = nullptr;
   P->gram_items = nullptr;
   P->gram_slot_off = nullptr;
+  P->gram_eta = nullptr;
   return LP_OK;
 }
 
@@ -1271,14 +1292,10 @@ lp_status lp_eta(lp_problem* P, int32_t iters, double* eta_out, double* per_part
   const int nb = eta_start_vectors();
   std::vector<double> inv_s(m), est((size_t)(m + 1) * nb);
   for (int i = 0; i < m; ++i) inv_s[i] = 1.0 / (double)(P->offsets[i + 1] - P->offsets[i]);
-  char* scratch = nullptr;
   lp_status st;
   if ((st = join_in(P)) != LP_OK) return st;
-  LP_HIP(hipStreamSynchronize(P->stream));
-  LP_HIP(hipMalloc((void**)&scratch, eta_scratch_bytes(P->d, m)));
-  hipError_t e = launch_eta(P->d, m, P->n, P->gram_M, inv_s.data(), iters, scratch, est.data(),
+  hipError_t e = launch_eta(P->d, m, P->n, P->gram_M, inv_s.data(), iters, P->gram_eta, est.data(),
                             P->stream);
-  (void)hipFree(scratch);
   if (e != hipSuccess) return fail(LP_EDEVICE, std::string("eta: ") + hipGetErrorString(e));
   auto row_max = [&](int b) {
     double v = 0.0;
@@ -1403,6 +1420,26 @@ lp_status lp_copy_probe(void* dst, const void* src, size_t bytes, int32_t iters,
   return LP_OK;
 }
 
+lp_status lp_generate(void* A, lp_dtype dtype, int64_t n, int64_t d, int64_t lda, int32_t k,
+                      double gap, double decay, uint64_t seed, double* U_out, void* stream) {
+  if (A == nullptr && U_out == nullptr) return fail(LP_EINVAL, "nothing to write (A and U_out NULL)");
+  if (!truth_shape_ok(n, d))
+    return fail(LP_EINVAL, "need d a power of two in [16, 8192] and n a positive multiple of d");
+  if (k < 1 || k > d) return fail(LP_EINVAL, "need 1 <= k <= d");
+  if (!(gap >= 1.0) || !(decay > 0.0 && decay <= 1.0))
+    return fail(LP_EINVAL, "need gap >= 1 and 0 < decay <= 1");
+  hipStream_t s = (hipStream_t)stream;
+  if (A != nullptr) {
+    if (dtype != LP_F32 && dtype != LP_BF16) return fail(LP_EINVAL, "A must be FP32 or BF16");
+    const uintptr_t align = dtype == LP_F32 ? 16 : 8;
+    if (lda < d || lda % 4 != 0 || ((uintptr_t)A % align) != 0)
+      return fail(LP_EINVAL, "need lda >= d, lda % 4 == 0 and A aligned to 4 elements");
+    LP_HIP(launch_truth_matrix(A, dtype, n, d, lda, k, gap, decay, seed, s));
+  }
+  if (U_out != nullptr) LP_HIP(launch_truth_basis(d, k, seed, U_out, s));
+  return LP_OK;
+}
+
 lp_status lp_sin_theta(const double* Z, const double* U, int64_t d, int32_t k, double* out_host,
                        void* stream) {
   return lp_sin_theta_r(Z, k, U, k, d, out_host, stream);
@@ -1414,11 +1451,15 @@ lp_status lp_sin_theta_r(const double* Z, int32_t r, const double* U, int32_t k,
   if (d < 1 || k < 1 || r < k || r > kMaxK || r > d)
     return fail(LP_EINVAL, "need 1 <= k <= r <= min(d, 64)");
   hipStream_t s = (hipStream_t)stream;
-  double* slot = nullptr;
-  LP_HIP(sin_slot_address(&slot));
-  LP_HIP(launch_sin_theta(d, r, k, Z, U, slot, nullptr, nullptr, s));
-  LP_HIP(hipMemcpyAsync(out_host, slot, sizeof(double), hipMemcpyDeviceToHost, s));
-  LP_HIP(hipStreamSynchronize(s));
+  double* cells = nullptr;
+  LP_HIP(sin_slot_address(&cells));
+  const int cell = take_sin_cell();
+  if (cell < 0) return fail(LP_EBUSY, "more than 64 sin theta calls in flight");
+  hipError_t e = launch_sin_theta(d, r, k, Z, U, cells + cell, nullptr, nullptr, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out_host, cells + cell, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  give_sin_cell(cell);
+  if (e != hipSuccess) return fail(LP_EDEVICE, std::string("sin theta: ") + hipGetErrorString(e));
   return LP_OK;
 }
 

@@ -52,6 +52,7 @@ struct Plan {
   LocalPath path;
   int32_t variant;           // fused kernel variant (see k_mfma.hip)
   bool nt_loads;             // nontemporal loads of A in the fused kernel
+  bool split_operands;       // BF16 A: hi + lo BF16 operand pairs (FP32-class results)
   int64_t min_chunk_rows;    // the default chunking the workspace was sized for
   Layout L;
 };
@@ -132,7 +133,7 @@ struct lp_problem {
   lp::WorkItem* gram_items = nullptr;
   int32_t* gram_slot_off = nullptr;   // [0..m]: i (one slot each); [m+1..2m+1]: 2 i
   bool gram_split2 = false;           // tbuf holds two partial Y_i per partition
-  void* blas = nullptr;            // rocBLAS handle for the one-time Gram products
+  char* gram_eta = nullptr;           // eta scratch inside the same buffer
 };
 
 namespace lp {
@@ -147,6 +148,9 @@ lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode);
 const double* drive_z(lp_problem* P);
 hipStream_t drive_stream(lp_problem* P);
 lp_status drive_breakdowns(lp_problem* P, int* breakdowns);
+// BF16 operand pairs in the fused BF16 kernel (lp_tuning.split_operands) without
+// the synchronising re-upload of lp_set_tuning (for a problem with no rounds yet).
+void drive_split_operands(lp_problem* P, bool split);
 // Record msg as the thread's last error (lp_last_error) and return s.
 lp_status report(lp_status s, const std::string& msg);
 
@@ -172,7 +176,7 @@ hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t ld
 
 // Fused single-pass matrix-core kernel: BF16 A, k in {16, 32}, d in {512, 1024,
 // 1536, 2048}, rows 16-byte aligned (BF16 operands, FP32 accumulation).
-bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A);
+bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A, bool split);
 hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
                                         const void* Zw, int64_t z_stride, void* part,
                                         const WorkItem* items, int nitems,
@@ -195,6 +199,10 @@ int eta_start_vectors();
 hipError_t launch_gram_multiply(const Plan& P, const float* M, int k, const void* Zw,
                                 int64_t z_stride, void* tbuf, const WorkItem* items, int m,
                                 int split, hipStream_t s);
+// Local-Gram form setup: M_i = A_i^T A_i (FP32, d x d row-major at M + i d d) for the
+// m partitions parts[i] = {i, i, first row, rows} (FP32 or BF16 A, d % 4 == 0).
+hipError_t launch_gram_products(const Plan& P, const void* A, int64_t lda, const WorkItem* parts,
+                                int m, float* M, hipStream_t s);
 hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda, int k,
                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                       const WorkItem* items, int nitems,
@@ -256,6 +264,16 @@ hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const doub
                             double* out, double* hist, int32_t* ctr, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
+
+// The library's own random inputs (k_gen.hip): count standard normals of the
+// start stream of `seed` (element e = i k + j of a d x k start); the exact-truth
+// matrix (FP32 or BF16, n x d with leading dimension lda; truth_shape_ok) and
+// its top-k right singular vectors U (d x k FP64).
+hipError_t launch_gaussian(int64_t count, uint64_t seed, double* Y, hipStream_t s);
+bool truth_shape_ok(int64_t n, int64_t d);
+hipError_t launch_truth_matrix(void* A, lp_dtype dtype, int64_t n, int64_t d, int64_t lda, int k,
+                               double gap, double decay, uint64_t seed, hipStream_t s);
+hipError_t launch_truth_basis(int64_t d, int k, uint64_t seed, double* U, hipStream_t s);
 // rho (Definition 3) of the m local iterates Zi (m x d x k, FP64) against the
 // first partition's, appended to hist[*ctr]; part: m doubles of scratch.
 hipError_t launch_rho(int m, int64_t d, int k, bool opt, const double* Zi, double* part,
@@ -266,7 +284,9 @@ hipError_t launch_stream_read(const void* buf, size_t bytes, hipStream_t s);
 // Copy `bytes` (a multiple of 16) from src to dst with the same streaming pattern.
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// Address of the library's one-double device result slot used by lp_sin_theta.
+// Address (on the current device) of the library's kSinSlots device result
+// cells used by lp_sin_theta; a call owns one cell from take to give back.
+constexpr int kSinSlots = 64;
 hipError_t sin_slot_address(double** p);
 
 // Y_i = sum of partials (item order, FP64) and the Gram partials of Y_i's row

@@ -11,6 +11,7 @@
 // therefore overlap on the GPU, and a finished job's slot is refilled at once
 // from the queue (continuous batching).
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -32,7 +33,9 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Job {
   uint64_t id = 0;
-  lp_job spec;
+  lp_job spec;                 // copied at submit, zero-extended for shorter structs
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
+  size_t a_bytes = 0;          // generated A inside the footprint (0: the caller's A)
   std::vector<int64_t> offsets;
   std::vector<double> y0;
   size_t ws_bytes = 0, footprint = 0;
@@ -73,11 +76,30 @@ struct lp_server {
 
 namespace {
 
+size_t elem(lp_dtype t) { return t == LP_F64 ? 8 : (t == LP_F32 ? 4 : 2); }
+
+// The caller's job zero-extended to the current struct (fields past its
+// struct_size read as zero: stream NULL, no generation).
+bool widen(const lp_job* j, lp_job* out) {
+  if (j == nullptr || j->struct_size < (int32_t)offsetof(lp_job, stream)) return false;
+  std::memset(out, 0, sizeof(*out));
+  std::memcpy(out, j, std::min<size_t>(sizeof(*out), (size_t)j->struct_size));
+  out->struct_size = sizeof(*out);
+  return true;
+}
+
 lp_status validate(const lp_job* j) {
-  if (j == nullptr || j->struct_size < (int32_t)sizeof(lp_job)) return lp::report(LP_EINVAL, "job is NULL or struct_size too small");
-  if (j->A == nullptr || j->offsets == nullptr || j->Y0 == nullptr || j->Z_out == nullptr)
-    return lp::report(LP_EINVAL, "A, offsets, Y0 and Z_out are required");
-  if (j->n < 1 || j->d < 1 || j->lda < j->d || j->m < 1) return lp::report(LP_EINVAL, "bad n, d, lda or m");
+  if (j->offsets == nullptr || j->Z_out == nullptr)
+    return lp::report(LP_EINVAL, "offsets and Z_out are required");
+  if (j->A == nullptr) {
+    if (j->dtype != LP_F32 && j->dtype != LP_BF16) return lp::report(LP_EINVAL, "generated A is FP32 or BF16");
+    if (!lp::truth_shape_ok(j->n, j->d))
+      return lp::report(LP_EINVAL, "generated A needs d a power of two in [16, 8192] and n a multiple of d");
+    if (!(j->gen_gap >= 1.0) || !(j->gen_decay > 0.0 && j->gen_decay <= 1.0))
+      return lp::report(LP_EINVAL, "generated A needs gen_gap >= 1 and 0 < gen_decay <= 1");
+  }
+  if (j->n < 1 || j->d < 1 || (j->A != nullptr && j->lda < j->d) || j->m < 1)
+    return lp::report(LP_EINVAL, "bad n, d, lda or m");
   if (j->k < 1 || j->k > 64 || j->k > j->d) return lp::report(LP_EINVAL, "need 1 <= k <= min(d, 64)");
   if (j->p0 < 1 || j->max_rounds < 1 || !(j->target > 0.0)) return lp::report(LP_EINVAL, "need p0 >= 1, max_rounds >= 1, target > 0");
   if (j->mode != LP_AGG_VANILLA && j->mode != LP_AGG_SIGN && j->mode != LP_AGG_OPT) return lp::report(LP_EINVAL, "unknown mode");
@@ -89,6 +111,10 @@ lp_status validate(const lp_job* j) {
 
 // bytes of the per-job buffers after the workspace: Y0, previous Z, change cell
 size_t extra_bytes(const lp_job* j) { return 2 * round_up((size_t)j->d * j->k * 8, 256) + 256; }
+// bytes of a generated A (none when the caller passes A)
+size_t gen_bytes(const lp_job* j) {
+  return j->A == nullptr ? round_up((size_t)j->n * j->d * elem(j->dtype), 256) : 0;
+}
 
 void publish(lp_server* S, Job* j, lp_status st) {
   lp_job_result r;
@@ -118,6 +144,8 @@ void release(lp_server* S, Job* j) {
   j->P = nullptr;
   if (j->mem != nullptr) (void)hipFreeAsync(j->mem, S->slot_stream[j->slot]);
   j->mem = nullptr;
+  if (j->ready != nullptr) (void)hipEventDestroy(j->ready);
+  j->ready = nullptr;
   S->free_slots.push_back(j->slot);
   j->slot = -1;
 }
@@ -161,25 +189,39 @@ lp_status start(lp_server* S, Job* j) {
   j->slot = S->free_slots.back();
   S->free_slots.pop_back();
   hipStream_t ss = S->slot_stream[j->slot];
+  // everything the caller queued on its stream before the submit comes first
+  if (hipStreamWaitEvent(ss, j->ready, 0) != hipSuccess)
+    return lp::report(LP_EDEVICE, "serving: wait for the caller's stream failed");
   if (hipMallocAsync((void**)&j->mem, j->footprint, ss) != hipSuccess) {
     j->mem = nullptr;
     return lp::report(LP_EDEVICE, "serving: allocation failed");
   }
-  const lp_job& sp = j->spec;
+  lp_job& sp = j->spec;
+  if (j->a_bytes > 0) {
+    // the job's own matrix, generated at admission after the buffers it uses
+    sp.A = j->mem + j->footprint - j->a_bytes;
+    sp.lda = sp.d;
+    if (lp::launch_truth_matrix((void*)sp.A, sp.dtype, sp.n, sp.d, sp.lda, sp.k, sp.gen_gap,
+                                sp.gen_decay, sp.gen_seed, ss) != hipSuccess)
+      return lp::report(LP_EDEVICE, "serving: generating A failed");
+  }
   lp_status st = lp_create(&j->P, sp.A, sp.dtype, sp.n, sp.d, sp.lda, j->offsets.data(), sp.m,
                            sp.k, j->mem, j->ws_bytes, ss);
   if (st != LP_OK) {
     j->P = nullptr;
     return st;
   }
+  if (sp.dtype == LP_BF16) lp::drive_split_operands(j->P, sp.single_bf16 == 0);
   const size_t dk8 = round_up((size_t)sp.d * sp.k * 8, 256);
   j->y0_dev = (double*)(j->mem + j->ws_bytes);
   j->zprev = (double*)(j->mem + j->ws_bytes + dk8);
   j->change_dev = (double*)(j->mem + j->ws_bytes + 2 * dk8);
   hipStream_t s = lp::drive_stream(j->P);
-  if (hipMemcpyAsync(j->y0_dev, j->y0.data(), (size_t)sp.d * sp.k * 8, hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return lp::report(LP_EDEVICE, "serving: start copy failed");
+  const hipError_t ey = j->y0.empty()
+                            ? lp::launch_gaussian((int64_t)sp.d * sp.k, sp.gen_seed, j->y0_dev, s)
+                            : hipMemcpyAsync(j->y0_dev, j->y0.data(), (size_t)sp.d * sp.k * 8,
+                                             hipMemcpyHostToDevice, s);
+  if (ey != hipSuccess) return lp::report(LP_EDEVICE, "serving: start copy failed");
   if ((st = lp::drive_begin(j->P, sp.k, j->y0_dev, false)) != LP_OK) return st;
   if (hipMemcpyAsync(j->zprev, lp::drive_z(j->P), (size_t)sp.d * sp.k * 8, hipMemcpyDeviceToDevice,
                      s) != hipSuccess)
@@ -222,6 +264,7 @@ void worker_main(lp_server* S) {
       if (S->stopping) {
         for (Job* j : S->queue) {
           S->used -= j->footprint;
+          if (j->ready != nullptr) (void)hipEventDestroy(j->ready);
           delete j;
         }
         S->queue.clear();
@@ -246,6 +289,7 @@ void worker_main(lp_server* S) {
       if (st != LP_OK) {
         if (j->P != nullptr) (void)hipStreamSynchronize(lp::drive_stream(j->P));
         if (j->slot >= 0) release(S, j);
+        else if (j->ready != nullptr) (void)hipEventDestroy(j->ready);
         publish(S, j, st);
         delete j;
         continue;
@@ -279,14 +323,16 @@ void worker_main(lp_server* S) {
 
 extern "C" {
 
-lp_status lp_server_footprint(const lp_job* job, size_t* bytes) {
+lp_status lp_server_footprint(const lp_job* job_in, size_t* bytes) {
   if (bytes == nullptr) return lp::report(LP_EINVAL, "bytes is NULL");
-  lp_status st = validate(job);
+  lp_job job;
+  if (!widen(job_in, &job)) return lp::report(LP_EINVAL, "job is NULL or struct_size too small");
+  lp_status st = validate(&job);
   if (st != LP_OK) return st;
   size_t ws = 0;
-  if ((st = lp_workspace_size(job->dtype, job->n, job->d, job->offsets, job->m, job->k, &ws)) != LP_OK)
+  if ((st = lp_workspace_size(job.dtype, job.n, job.d, job.offsets, job.m, job.k, &ws)) != LP_OK)
     return st;
-  *bytes = round_up(ws, 256) + extra_bytes(job);
+  *bytes = round_up(ws, 256) + extra_bytes(&job) + gen_bytes(&job);
   return LP_OK;
 }
 
@@ -321,24 +367,35 @@ lp_status lp_server_create(lp_server** out, size_t hbm_budget_bytes, int32_t max
   return LP_OK;
 }
 
-lp_status lp_server_submit(lp_server* S, const lp_job* job, uint64_t* job_id) {
+lp_status lp_server_submit(lp_server* S, const lp_job* job_in, uint64_t* job_id) {
   if (S == nullptr || job_id == nullptr) return lp::report(LP_EINVAL, "server or job_id is NULL");
   size_t fp = 0;
-  lp_status st = lp_server_footprint(job, &fp);
+  lp_status st = lp_server_footprint(job_in, &fp);
   if (st != LP_OK) return st;
   if (fp > S->budget) return lp::report(LP_ENOMEM, "job footprint exceeds the server budget");
+  lp_job job;
+  widen(job_in, &job);
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, (hipStream_t)job.stream) != hipSuccess) {
+    if (ready != nullptr) (void)hipEventDestroy(ready);
+    return lp::report(LP_EDEVICE, "serving: event on the caller's stream failed");
+  }
   Job* j = new Job();
-  j->spec = *job;
-  j->offsets.assign(job->offsets, job->offsets + job->m + 1);
+  j->spec = job;
+  j->ready = ready;
+  j->offsets.assign(job.offsets, job.offsets + job.m + 1);
   j->spec.offsets = nullptr;
-  j->y0.assign(job->Y0, job->Y0 + (size_t)job->d * job->k);
+  if (job.Y0 != nullptr) j->y0.assign(job.Y0, job.Y0 + (size_t)job.d * job.k);
   j->spec.Y0 = nullptr;
   j->footprint = fp;
-  j->ws_bytes = fp - extra_bytes(job);
+  j->a_bytes = gen_bytes(&job);
+  j->ws_bytes = fp - extra_bytes(&job) - j->a_bytes;
   j->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stopping) {
+      (void)hipEventDestroy(j->ready);
       delete j;
       return lp::report(LP_EBUSY, "server is stopping");
     }

@@ -82,3 +82,33 @@ def test_abi_from_plain_c(tmp_path):
     assert int(nbytes) == _lib.lp_workspace_size(torch.float64, 2000, 100,
                                                  np.array([0, 500, 1000, 1500, 2000]), 5)
     assert out[1].startswith(f"{_lib.LP_EINVAL} ") and out[2]
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding passes across the ABI has the C compiler's size
+    and field offsets (a missing or misplaced field would shift the rest)."""
+    import ctypes
+    import shutil
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "abi_layout")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I" + os.path.join(ROOT, "include"), "-o", exe,
+                    os.path.join(ROOT, "tests", "host", "abi_layout.c")], check=True)
+    lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    from paper_2002_08014_amd import _lib
+    types = {"lp_run_opts": _lib.RunOpts, "lp_solve_opts": _lib.SolveOpts, "lp_run_stats": _lib.RunStats,
+             "lp_solve_stats": _lib.SolveStats, "lp_tuning": _lib.Tuning, "lp_job": _lib.Job,
+             "lp_job_result": _lib.JobResult}
+    checked = 0
+    for ln in lines:
+        if not ln:
+            continue
+        name, val = ln.split()
+        if "." in name:
+            t, f = name.split(".")
+            assert getattr(types[t], f).offset == int(val), name
+        else:
+            assert ctypes.sizeof(types[name]) == int(val), name
+        checked += 1
+    assert checked > 40

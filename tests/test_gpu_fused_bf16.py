@@ -133,3 +133,59 @@ def test_bf16_fused_run_parity(lp, mode):
         aligned = [t for t, sv in enumerate(ro["signs"]) if sv is not None]   # rounds with p >= 2
         assert aligned
         assert np.array_equal(r["signs"][aligned], np.stack([ro["signs"][t] for t in aligned]))
+
+
+# ---------------------------------------------------------------- split operand pairs
+
+def _check_split(Y, A, offsets, Zw, parts):
+    """Operand pairs hi + lo leave |x - hi - lo| <= 2^-17 |x| (x - hi is exact in
+    FP32, lo rounds it once), so each entry obeys
+      |Y - A^T A Z| <= (2^-16 + (d + s) u_32) (1 + 4 u_b) |A|^T (|A| |Z|)."""
+    for i in parts:
+        Ai = A[offsets[i]:offsets[i + 1]]
+        ref = Ai.T @ (Ai @ Zw)
+        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+        fac = (2.0 ** -16 + (Ai.shape[1] + Ai.shape[0]) * U_32) * (1 + 4 * U_B)
+        err = np.abs(Y[i] - ref)
+        assert np.all(err <= fac * bound), (i, float((err / np.maximum(bound, 1e-300)).max()), fac)
+
+
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
+@pytest.mark.parametrize("k", [16, 32])
+@pytest.mark.parametrize("d", [512, 1024, 1536, 2048])
+def test_bf16_split_operands_small(lp, d, k, variant):
+    print(f"bf16 split operands d={d} k={k} variant={variant}", flush=True)
+    n, m = 3 * d + 37, 3
+    w = synth.make_small(n, d, k, m, seed=d + k + 1, dtype=torch.bfloat16, uneven=True)
+    A_dev = w.A.to("cuda:0")
+    P = lp.lp_create(A_dev, w.offsets, k)
+    lp.lp_set_tuning(P, variant, 0, False, True)
+    assert lp.lp_get_tuning(P)["split_operands"]
+    Z = oracle.orth(np.random.default_rng(d + k + 1).standard_normal((d, k)))
+    Y = host(lp.lp_local_multiply(P, k, torch.as_tensor(Z)))
+    Zw = Z.astype(np.float32).astype(np.float64)
+    if k == 32 and d == 2048:
+        # the pairs do not fit: the two-pass kernel with FP32 operands runs
+        for i in range(m):
+            Ai = upcast(A_dev)[w.offsets[i]:w.offsets[i + 1]]
+            bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+            assert np.all(np.abs(Y[i] - Ai.T @ (Ai @ Zw)) <= (d + Ai.shape[0]) * U_32 * bound)
+    else:
+        _check_split(Y, upcast(A_dev), w.offsets, Zw, range(m))
+
+
+def test_bf16_split_operands_run_parity(lp):
+    """A whole run with operand pairs (d = 1024, k = 16) is FP32-class: within
+    1e-5 of the oracle on the same BF16 values (single roundings sit near 1e-3)."""
+    print("bf16 split operands run", flush=True)
+    sched = synth.decay_schedule((4, 2, 1), 5)
+    w64 = synth.make_small(32768, 1024, 16, 4, seed=22, dtype=torch.float64, gap=1.3, p_sched=sched)
+    A_dev = w64.A.to(torch.bfloat16).to("cuda:0")
+    P = lp.lp_create(A_dev, w64.offsets, 16)
+    ro = oracle.localpower(upcast(A_dev), w64.offsets, 16, sched, "opt", w64.Y0)
+    single = host(lp.lp_run(P, 16, sched, "opt", w64.Y0)["Z"])
+    lp.lp_set_tuning(P, 0, 0, False, True)
+    split = host(lp.lp_run(P, 16, sched, "opt", w64.Y0)["Z"])
+    s_single, s_split = sin_theta_np(single, ro["Z"]), sin_theta_np(split, ro["Z"])
+    print(f"single BF16 {s_single:.2e}, pairs {s_split:.2e}", flush=True)
+    assert s_split < 1e-5 and s_split < s_single / 10
