@@ -317,6 +317,21 @@ lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y
 lp_status lp_orth(lp_problem* P, int32_t k, int32_t batch, const double* Y, double* Q,
                   int32_t* flags);
 
+/* lp_orth for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same batched CholeskyQR2,
+ * Q_b = orth(Y_b) for b < batch, each d x k FP64 (device; Q may alias Y), flags as
+ * in lp_orth, enqueued on `stream`, with no problem and no allocation.  Its
+ * scratch is a 16 MiB array in the library's static device memory, one per GPU,
+ * held from the first call on that GPU until the process ends:
+ * 8 (batch (d k + 2 ceil(d / 64) k^2 + 2 k^2)) bytes, each of the four parts
+ * rounded up to 256, must fit (for example one 4096 x 64 matrix, or 64 matrices of
+ * 1024 x 16); larger batches get LP_EINVAL.  All calls on one GPU share that
+ * scratch: calls that overlap in time on one GPU (different streams or threads)
+ * race and must be serialised by the caller.  1 <= k <= min(d, 64), batch >= 1.
+ * Asynchronous. */
+lp_status lp_orth_noalloc(int32_t k, int32_t batch, int64_t d, const double* Y, double* Q,
+                          int32_t* flags, void* stream);
+
 /* Alignment of batch iterates Zi (device, batch x d x k FP64) against Zb (device
  * d x k FP64):
  *   LP_AGG_SIGN: out is device int8[batch*k], sgn(<Zi[:,j], Zb[:,j]>) with sgn(0)=+1;

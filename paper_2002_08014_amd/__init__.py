@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     lp_eta,
     lp_local_multiply,
     lp_orth,
+    lp_orth_noalloc,
     lp_align,
     lp_sin_theta,
     lp_generate,

@@ -24,7 +24,8 @@ MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_gram_bytes",
-           "lp_gram_enable", "lp_gram_disable", "lp_eta", "lp_local_multiply", "lp_orth", "lp_align",
+           "lp_gram_enable", "lp_gram_disable", "lp_eta", "lp_local_multiply", "lp_orth", "lp_orth_noalloc",
+           "lp_align",
            "lp_sin_theta", "lp_sin_theta_r", "lp_generate", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
            "lp_server_destroy")
@@ -174,6 +175,8 @@ def load() -> ctypes.CDLL:
     L.lp_local_multiply.argtypes = [vp, i32, vp, vp]
     L.lp_orth.restype = i32
     L.lp_orth.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.lp_orth_noalloc.restype = i32
+    L.lp_orth_noalloc.argtypes = [i32, i32, i64, vp, vp, vp, vp]
     L.lp_align.restype = i32
     L.lp_align.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     L.lp_bandwidth_probe.restype = i32
@@ -446,6 +449,25 @@ def lp_orth(P: Problem, Y: torch.Tensor):
     Q = torch.empty_like(Y)
     flags = torch.zeros(b, dtype=torch.int32, device=Y.device)
     _check(L.lp_orth(P.handle, k, b, _ptr(Y), _ptr(Q), _ptr(flags)), "lp_orth")
+    return Q, flags
+
+
+def lp_orth_noalloc(Y: torch.Tensor, Q: Optional[torch.Tensor] = None,
+                    flags: Optional[torch.Tensor] = None,
+                    stream: Optional[torch.cuda.Stream] = None):
+    """lp_orth without a problem or an allocation inside the library (its scratch is
+    static device memory shared by every call on the GPU).  Y: batch x d x k (or
+    d x k) float64 device; Q (same shape) and flags (int32[batch]) may be passed in,
+    e.g. to stay allocation-free under graph capture.  Returns (Q, flags)."""
+    L = load()
+    Y3 = Y if Y.dim() == 3 else Y[None]
+    if not Y3.is_contiguous():
+        raise ValueError("Y must be contiguous")
+    b, d, k = Y3.shape
+    Q = torch.empty_like(Y) if Q is None else Q
+    flags = torch.zeros(b, dtype=torch.int32, device=Y.device) if flags is None else flags
+    _check(L.lp_orth_noalloc(k, b, d, _ptr(Y3), _ptr(Q), _ptr(flags), _stream_handle(stream)),
+           "lp_orth_noalloc")
     return Q, flags
 
 

@@ -176,6 +176,20 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
 }
 
+hipError_t cholqr2_passes(int batch, int64_t d, int k, const double* Y, const double* gram,
+                          double* gram2, double* tmp, double* rfac, double* Q, void* zw,
+                          size_t zw_bytes, int32_t* flags, hipStream_t s) {
+  const int nch = (int)((d + kGramRows - 1) / kGramRows);
+  hipError_t e;
+  // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}, and the Gram partials of Q1
+  if ((e = launch_chol_solve(batch, d, k, nch, Y, gram, rfac, tmp, nullptr, 0, gram2, flags, s)) !=
+      hipSuccess)
+    return e;
+  // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1} (and the working copy)
+  return launch_chol_solve(batch, d, k, chol_solve_chunks(d, k), tmp, gram2, rfac, Q, zw,
+                           zw_bytes, nullptr, flags, s);
+}
+
 hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y,
                              double* Q, void* zw, int32_t* flags, hipStream_t s, int b0) {
   const Layout& L = P.L;
@@ -185,14 +199,7 @@ hipError_t cholqr2_from_gram(const Plan& P, char* ws, int batch, int64_t d, int 
   double* gram2 = (double*)(ws + L.gram2) + (int64_t)b0 * nch * kk;
   double* tmp = (double*)(ws + L.tmp) + (int64_t)b0 * d * k;
   double* rfac = (double*)(ws + L.rinv) + (int64_t)b0 * 2 * kk;
-  hipError_t e;
-  // pass 1: R1 = chol(Y^T Y), Q1 = Y R1^{-1}, and the Gram partials of Q1
-  if ((e = launch_chol_solve(batch, d, k, nch, Y, gram, rfac, tmp, nullptr, 0, gram2, flags, s)) !=
-      hipSuccess)
-    return e;
-  // pass 2: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1} (and the working copy)
-  return launch_chol_solve(batch, d, k, chol_solve_chunks(d, k), tmp, gram2, rfac, Q, zw,
-                           P.zw_bytes, nullptr, flags, s);
+  return cholqr2_passes(batch, d, k, Y, gram, gram2, tmp, rfac, Q, zw, P.zw_bytes, flags, s);
 }
 
 hipError_t cholqr2(const Plan& P, char* ws, int batch, int64_t d, int k, const double* Y, double* Q,

@@ -319,6 +319,13 @@ hipError_t launch_diag_dot(int batch, int64_t d, int k, const double* Zi, const 
 hipError_t launch_sign_apply(int batch, int64_t d, int k, const double* part, double* Zi, void* zw,
                              size_t zw_bytes, int8_t* sgn, hipStream_t s);
 
+// The two CholeskyQR passes on explicit buffers: gram holds the Gram partials of
+// the batch of Y's (ceil(d / 64) k x k partials per matrix); gram2 (the same
+// size), tmp (batch d k) and rfac (batch 2 k^2) are scratch; Q may alias Y.
+hipError_t cholqr2_passes(int batch, int64_t d, int k, const double* Y, const double* gram,
+                          double* gram2, double* tmp, double* rfac, double* Q, void* zw,
+                          size_t zw_bytes, int32_t* flags, hipStream_t s);
+
 // CholeskyQR2 when the Gram partials of Y are already in the plan's gram buffer.
 // b0: index of the first matrix of the batch among the plan's matrices (its
 // partials and scratch are at that offset, so disjoint batches may run
