@@ -111,6 +111,9 @@ lp_status lp_destroy(lp_problem* P);
  *                 BF16 A (k in {16, 32}, d in {512, 1024, 1536, 2048}; Z and t rounded to
  *                 BF16 as operands): 2 four waves; 3 eight waves (d in {1024, 2048});
  *                 4 and 5 the same with two tiles in flight per wave.
+ *                 Ranks k <= 8 (FP32 or BF16 A, d a power of two in [256, 4096]) run a
+ *                 fused vector-ALU kernel (A read once, FP32 arithmetic, no matrix
+ *                 cores) unless local_kernel = 1 asks for the two-pass kernel.
  *                 Other shapes and ranks use the two-pass kernel.
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
  *                 default chosen at lp_create, which sized the workspace); 0 = default.

@@ -108,6 +108,7 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   P->variant = 1;
   P->nt_loads = true;
   P->split_operands = false;
+  P->valu = true;
   build_items(P, offsets, cr);
   P->n_gram_chunks = (int32_t)((d + kGramRows - 1) / kGramRows);
   const size_t dk = (size_t)d * k_max;
@@ -167,6 +168,8 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
                                  int64_t z_stride, void* tbuf, void* part,
                                  const WorkItem* items_dev, int nitems, hipStream_t s) {
   if (nitems < 1) return hipSuccess;
+  if (P.valu && valu_eligible(P.dtype, P.d, lda, k, A))
+    return launch_local_multiply_valu(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (P.path == LocalPath::Mfma32 && mfma32_eligible(P.dtype, P.d, lda, k))
     return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A, P.split_operands))
@@ -549,8 +552,9 @@ LocalPath fused_kind(const lp_problem* P) {
   return LocalPath::TwoPass;
 }
 
-// Whether the fused kernel handles this k.
+// Whether a fused (single-pass) kernel handles this k.
 bool fused_for_k(const lp_problem* P, int k) {
+  if (P->plan.valu && valu_eligible(P->dtype, P->d, P->lda, k, P->A)) return true;
   switch (fused_kind(P)) {
     case LocalPath::Mfma32: return mfma32_eligible(P->dtype, P->d, P->lda, k);
     case LocalPath::MfmaBf16:
@@ -808,6 +812,7 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   }
   P->plan.nt_loads = t->cached_loads == 0;
   P->plan.split_operands = t->split_operands != 0;
+  P->plan.valu = t->local_kernel != 1;
   build_items(&P->plan, P->offsets.data(), cr);
   return upload_items(P);
 }
@@ -903,11 +908,16 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
   }
   const int32_t split = P->plan.split_operands ? 1 : 0;   // kept: a choice of accuracy
   const bool fused_ok = fused_for_k(P, k);
+  // k <= 8 on the vector-ALU kernel: only the work-item size varies (the matrix
+  // cores serve k >= 16)
+  const bool valu_k = P->plan.valu && valu_eligible(P->dtype, P->d, P->lda, k, P->A);
   const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 10 : 5;
   std::vector<lp_tuning> cand;
   const int64_t c0 = P->plan.min_chunk_rows;
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
-    if (fused_ok) {
+    if (valu_k) {
+      cand.push_back({(int32_t)sizeof(lp_tuning), 0, cr, 0, split});
+    } else if (fused_ok) {
       for (int lk = 2; lk <= lk_max; ++lk)
         for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, split});
     } else {
@@ -998,6 +1008,7 @@ lp_status lp_run(lp_problem* P, int32_t k, const int32_t* p_sched, int32_t T, lp
   bool split;
   {
     const bool fused =
+        (P->plan.valu && valu_eligible(P->dtype, P->d, P->lda, k, P->A)) ||
         (P->plan.path == LocalPath::Mfma32 && mfma32_eligible(P->dtype, P->d, P->lda, k)) ||
         (P->plan.path == LocalPath::MfmaBf16 &&
          mfma16_eligible(P->dtype, P->d, P->lda, k, P->A, P->plan.split_operands));

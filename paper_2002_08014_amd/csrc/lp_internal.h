@@ -53,6 +53,7 @@ struct Plan {
   int32_t variant;           // fused kernel variant (see k_mfma.hip)
   bool nt_loads;             // nontemporal loads of A in the fused kernel
   bool split_operands;       // BF16 A: hi + lo BF16 operand pairs (FP32-class results)
+  bool valu;                 // k <= 8: the fused vector-ALU kernel (off: two-pass kernel)
   int64_t min_chunk_rows;    // the default chunking the workspace was sized for
   Layout L;
 };
@@ -181,6 +182,13 @@ hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t ld
                                         const void* Zw, int64_t z_stride, void* part,
                                         const WorkItem* items, int nitems,
                                         hipStream_t s);
+
+// Fused single-pass vector-ALU kernel for small ranks: FP32 or BF16 A, k <= 8,
+// d a power of two in [256, 4096], rows aligned to 16 bytes.
+bool valu_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A);
+hipError_t launch_local_multiply_valu(const Plan& P, const void* A, int64_t lda, int k,
+                                      const void* Zw, int64_t z_stride, void* part,
+                                      const WorkItem* items, int nitems, hipStream_t s);
 
 // Two-pass form on FP32 matrix cores (t = A Z, then A^T t): FP32 or BF16 A,
 // d % 4 == 0, any k <= 64.
