@@ -17,9 +17,9 @@
 //     threads, then the blocks), in a fixed order;
 //   * product 2: every thread of the group reads the group's t (broadcast) and
 //     adds A_rows^T t to its Y columns.
-// The next step's rows are loaded into registers while the current step
-// computes.  At the end the row groups' Y partials are summed through LDS in a
-// fixed order and written as the item's partial.  K is the rank padded to 1,
+// The next one or two steps' rows are loaded into registers (kept packed)
+// while the current step computes.  At the end the row groups' Y partials are
+// summed through LDS in a fixed order and written as the item's partial.  K is the rank padded to 1,
 // 2, 4 or 8 (padding columns of Z are zero and are not written).
 #include "lp_internal.h"
 
@@ -32,30 +32,45 @@ constexpr int kCPT = 8;      // columns per thread
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// eight columns of one row as FP32
-__device__ inline void load8(const float* row, int tl, int TPR, bool ok, float (&a)[kCPT]) {
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+// One row's eight columns as loaded (FP32: two 16-byte chunks; BF16: one), kept
+// packed while in flight and widened to FP32 when their step computes.
+template <typename TA>
+struct Raw;
+template <>
+struct Raw<float> {
+  f4 x, y;
+};
+template <>
+struct Raw<__hip_bfloat16> {
+  u4 v;
+};
+
+__device__ inline void load_raw(const float* row, int tl, int TPR, bool ok, Raw<float>& r) {
   if (ok) {
-    const f4 x = __builtin_nontemporal_load((const f4*)(row + 4 * tl));
-    const f4 y = __builtin_nontemporal_load((const f4*)(row + 4 * (tl + TPR)));
-    a[0] = x[0]; a[1] = x[1]; a[2] = x[2]; a[3] = x[3];
-    a[4] = y[0]; a[5] = y[1]; a[6] = y[2]; a[7] = y[3];
+    r.x = __builtin_nontemporal_load((const f4*)(row + 4 * tl));
+    r.y = __builtin_nontemporal_load((const f4*)(row + 4 * (tl + TPR)));
   } else {
-#pragma unroll
-    for (int c = 0; c < kCPT; ++c) a[c] = 0.f;
+    r.x = r.y = f4{0.f, 0.f, 0.f, 0.f};
   }
 }
-__device__ inline void load8(const __hip_bfloat16* row, int tl, int /*TPR*/, bool ok, float (&a)[kCPT]) {
-  if (ok) {
-    typedef unsigned u4 __attribute__((ext_vector_type(4)));
-    const u4 v = __builtin_nontemporal_load((const u4*)(row + 8 * tl));
+__device__ inline void load_raw(const __hip_bfloat16* row, int tl, int /*TPR*/, bool ok,
+                                Raw<__hip_bfloat16>& r) {
+  if (ok)
+    r.v = __builtin_nontemporal_load((const u4*)(row + 8 * tl));
+  else
+    r.v = u4{0u, 0u, 0u, 0u};
+}
+__device__ inline void widen(const Raw<float>& r, float (&a)[kCPT]) {
+  a[0] = r.x[0]; a[1] = r.x[1]; a[2] = r.x[2]; a[3] = r.x[3];
+  a[4] = r.y[0]; a[5] = r.y[1]; a[6] = r.y[2]; a[7] = r.y[3];
+}
+__device__ inline void widen(const Raw<__hip_bfloat16>& r, float (&a)[kCPT]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      a[2 * q] = __uint_as_float(v[q] << 16);
-      a[2 * q + 1] = __uint_as_float(v[q] & 0xffff0000u);
-    }
-  } else {
-#pragma unroll
-    for (int c = 0; c < kCPT; ++c) a[c] = 0.f;
+  for (int q = 0; q < 4; ++q) {
+    a[2 * q] = __uint_as_float(r.v[q] << 16);
+    a[2 * q + 1] = __uint_as_float(r.v[q] & 0xffff0000u);
   }
 }
 
@@ -68,7 +83,9 @@ __device__ inline int col_of(int tl, int TPR, int c) {
     return 8 * tl + c;
 }
 
-template <typename TA, int K>
+// PF: steps in flight ahead of the one computing (1 or 2; two where the
+// registers allow: BF16 rows are half as wide while packed)
+template <typename TA, int K, int PF>
 __global__ void __launch_bounds__(kThreads, 1)
 k1_valu(const TA* __restrict__ A, int64_t lda, int d, int k, const float* __restrict__ Zw,
         int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
@@ -102,74 +119,80 @@ k1_valu(const TA* __restrict__ A, int64_t lda, int d, int k, const float* __rest
 
   const int step_rows = RG * kR;
   const int nsteps = (rows + step_rows - 1) / step_rows;
-  float a[kR][kCPT], an[kR][kCPT];
-  auto load_step = [&](int s, float (&dst)[kR][kCPT]) {
+  Raw<TA> raw[PF][kR];
+  auto load_step = [&](int st, Raw<TA> (&dst)[kR]) {
 #pragma unroll
     for (int i = 0; i < kR; ++i) {
-      const int r = s * step_rows + rg * kR + i;
-      load8(Ab + (int64_t)min(r, rows - 1) * lda, tl, TPR, r < rows, dst[i]);
+      const int r = st * step_rows + rg * kR + i;
+      load_raw(Ab + (int64_t)min(r, rows - 1) * lda, tl, TPR, r < rows, dst[i]);
     }
   };
-  load_step(0, a);
-  for (int s = 0; s < nsteps; ++s) {
-    if (s + 1 < nsteps) load_step(s + 1, an);
-    // product 1: partial t over this thread's columns
-    float p[V];
 #pragma unroll
-    for (int i = 0; i < kR; ++i)
+  for (int q = 0; q < PF; ++q)
+    if (q < nsteps) load_step(q, raw[q]);
+  for (int s0 = 0; s0 < nsteps; s0 += PF) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
+    for (int q = 0; q < PF; ++q) {
+      const int s = s0 + q;
+      if (s >= nsteps) break;
+      float a[kR][kCPT];
+#pragma unroll
+      for (int i = 0; i < kR; ++i) widen(raw[q][i], a[i]);
+      if (s + PF < nsteps) load_step(s + PF, raw[q]);
+      // product 1: partial t over this thread's columns
+      float p[V];
+#pragma unroll
+      for (int i = 0; i < kR; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          float acc = 0.f;
+#pragma unroll
+          for (int c = 0; c < kCPT; ++c) acc = fmaf(a[i][c], z[c][j], acc);
+          p[i * K + j] = acc;
+        }
+      float* mine = &pbuf[(rg * TPR + tl) * PS];
+#pragma unroll
+      for (int v = 0; v < V; v += 4) *(f4*)&mine[v] = f4{p[v], p[v + 1], p[v + 2], p[v + 3]};
+      __syncthreads();
+      // level 1: output v = tl % V over the V consecutive threads of block tl / V
+      {
+        const int v = tl % V, b = tl / V;
+        const float* src = &pbuf[(rg * TPR + b * V) * PS + v];
         float acc = 0.f;
 #pragma unroll
-        for (int c = 0; c < kCPT; ++c) acc = fmaf(a[i][c], z[c][j], acc);
-        p[i * K + j] = acc;
-      }
-    float* mine = &pbuf[(rg * TPR + tl) * PS];
-#pragma unroll
-    for (int v = 0; v < V; v += 4) *(f4*)&mine[v] = f4{p[v], p[v + 1], p[v + 2], p[v + 3]};
-    __syncthreads();
-    // level 1: output v = tl % V over the V consecutive threads of block tl / V
-    {
-      const int v = tl % V, b = tl / V;
-      const float* src = &pbuf[(rg * TPR + b * V) * PS + v];
-      float acc = 0.f;
-#pragma unroll
-      for (int u = 0; u < V; ++u) acc += src[u * PS];
-      if (NB == 1)
-        tsh[rg * V + v] = acc;
-      else
-        l1[rg * TPR + b * V + v] = acc;
-    }
-    __syncthreads();
-    if (NB > 1) {
-      // level 2: the NB block sums of each output, in block order
-      if (tl < V) {
-        float acc = 0.f;
-        for (int b = 0; b < NB; ++b) acc += l1[rg * TPR + b * V + tl];
-        tsh[rg * V + tl] = acc;
+        for (int u = 0; u < V; ++u) acc += src[u * PS];
+        if (NB == 1)
+          tsh[rg * V + v] = acc;
+        else
+          l1[rg * TPR + b * V + v] = acc;
       }
       __syncthreads();
-    }
-    // product 2: Y += A_rows^T t
-    float t[V];
+      if (NB > 1) {
+        // level 2: the NB block sums of each output, in block order
+        if (tl < V) {
+          float acc = 0.f;
+          for (int b = 0; b < NB; ++b) acc += l1[rg * TPR + b * V + tl];
+          tsh[rg * V + tl] = acc;
+        }
+        __syncthreads();
+      }
+      // product 2: Y += A_rows^T t
+      float t[V];
 #pragma unroll
-    for (int v = 0; v < V; v += 4) {
-      const f4 q = *(const f4*)&tsh[rg * V + v];
-      t[v] = q[0]; t[v + 1] = q[1]; t[v + 2] = q[2]; t[v + 3] = q[3];
-    }
-#pragma unroll
-    for (int c = 0; c < kCPT; ++c)
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        float acc = y[c][j];
-#pragma unroll
-        for (int i = 0; i < kR; ++i) acc = fmaf(a[i][c], t[i * K + j], acc);
-        y[c][j] = acc;
+      for (int v = 0; v < V; v += 4) {
+        const f4 qv = *(const f4*)&tsh[rg * V + v];
+        t[v] = qv[0]; t[v + 1] = qv[1]; t[v + 2] = qv[2]; t[v + 3] = qv[3];
       }
 #pragma unroll
-    for (int i = 0; i < kR; ++i)
+      for (int c = 0; c < kCPT; ++c)
 #pragma unroll
-      for (int c = 0; c < kCPT; ++c) a[i][c] = an[i][c];
+        for (int j = 0; j < K; ++j) {
+          float acc = y[c][j];
+#pragma unroll
+          for (int i = 0; i < kR; ++i) acc = fmaf(a[i][c], t[i * K + j], acc);
+          y[c][j] = acc;
+        }
+    }
   }
 
   // the item's partial: the row groups' Y summed in group order
@@ -207,8 +230,11 @@ k1_valu(const TA* __restrict__ A, int64_t lda, int d, int k, const float* __rest
 template <typename TA, int K>
 hipError_t launch_k(int64_t d, int k, const void* A, int64_t lda, const void* Zw, int64_t z_stride,
                     void* part, const WorkItem* items, int nitems, hipStream_t s) {
-  k1_valu<TA, K><<<nitems, kThreads, 0, s>>>((const TA*)A, lda, (int)d, k, (const float*)Zw, z_stride,
-                                             items, (float*)part);
+  // two steps in flight where the registers hold them without spilling (BF16
+  // up to K = 4, FP32 up to K = 2), else one
+  constexpr int PF = (sizeof(TA) == 2 ? K <= 4 : K <= 2) ? 2 : 1;
+  k1_valu<TA, K, PF><<<nitems, kThreads, 0, s>>>((const TA*)A, lda, (int)d, k, (const float*)Zw,
+                                                 z_stride, items, (float*)part);
   return hipGetLastError();
 }
 
