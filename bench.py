@@ -398,6 +398,48 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def load_balance(lp, w, k):
+    """How evenly one two-pass local multiply over the uneven partitions uses the
+    GPU, from per-workgroup start/end stamps (lp_profile_local_multiply, default
+    work-item size): workgroup busy times, the busy time per row of every
+    partition, and per pass the busy fraction of the launch (sum of busy times over
+    span x the largest number of workgroups seen running at once)."""
+    P = lp.lp_create(w.A, w.offsets, k)
+    cr = lp.lp_get_tuning(P)["chunk_rows"]
+    Z = np.linalg.qr(np.random.default_rng(0).standard_normal((w.d, k)))[0]
+    st = lp.lp_profile_local_multiply(P, k, Z)
+    lp.lp_destroy(P)
+    item_part, item_rows = [], []
+    for i in range(w.m):
+        for r in range(int(w.offsets[i]), int(w.offsets[i + 1]), cr):
+            item_part.append(i)
+            item_rows.append(min(cr, int(w.offsets[i + 1]) - r))
+    item_part, item_rows = np.array(item_part), np.array(item_rows)
+    out = {"work_item_rows": int(cr), "items": int(len(item_rows)), "workgroups": int(len(st))}
+    busy_part = np.zeros(w.m)
+    for ps in (1, 2):
+        sel = st[st[:, 0] == ps]
+        busy = sel[:, 3] - sel[:, 2]
+        live = busy > 0
+        full = live & (item_rows[sel[:, 1].astype(int)] == cr)
+        ev = sorted([(t, 1) for t in sel[live, 2]] + [(t, -1) for t in sel[live, 3]])
+        cur = peak = 0
+        for _, dlt in ev:
+            cur += dlt
+            peak = max(peak, cur)
+        span = float(sel[live, 3].max() - sel[live, 2].min())
+        np.add.at(busy_part, item_part[sel[:, 1].astype(int)], busy)
+        out[f"pass{ps}"] = {"span_us": round(span, 1), "peak_concurrent_workgroups": int(peak),
+                            "busy_fraction": round(float(busy[live].sum()) / (span * peak), 4),
+                            "workgroup_busy_us_max": round(float(busy[live].max()), 2),
+                            "workgroup_busy_us_min": round(float(busy[live].min()), 2),
+                            "full_item_busy_max_over_min": round(float(busy[full].max() / busy[full].min()), 3)}
+    rate = busy_part / np.diff(np.asarray(w.offsets))
+    out["partition_busy_us_per_row_max_over_min"] = round(float(rate.max() / rate.min()), 3)
+    out["partition_rows_max_over_min"] = round(float(np.diff(w.offsets).max() / np.diff(w.offsets).min()), 2)
+    return out
+
+
 def measure(lp, synth, name, args, steps, warmup, headline=False):
     """Generate one workload, autotune, time `steps` steps (each step runs the
     workload's schedule once per alignment mode) after `warmup` untimed ones, and
@@ -538,6 +580,9 @@ def measure(lp, synth, name, args, steps, warmup, headline=False):
     if headline and args.trends and name == "fp32-262144x1024":
         log("floors over p and m")
         rec["trends"] = trends(lp, synth, w, k)
+    if name == "fp32-uneven-500000x4096":
+        log("load balance of the uneven partitions (workgroup stamps)")
+        rec["load_balance"] = load_balance(lp, w, k)
     if args.precision and name == "bf16-1048576x2048":
         rec["precision"] = precision_report(lp, synth, w, P, tuning, sched)
     if not args.no_cpu_baseline:

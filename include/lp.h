@@ -313,6 +313,17 @@ lp_status lp_eta(lp_problem* P, int32_t iters, double* eta_out, double* per_part
  * Enqueued on the problem's stream; asynchronous. */
 lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y_out);
 
+/* One two-pass local multiply (as lp_local_multiply, without the reduction) with a
+ * start and end stamp of every workgroup (the GPU's constant-rate wall clock), for
+ * measuring how evenly uneven partitions spread over the GPU.  wg_out: host
+ * [max_wg x 4] FP64 rows (pass 1 or 2, work-item index, start us, end us, times
+ * relative to the earliest start); *n_wg receives the number of workgroups (also
+ * when max_wg is too small, which returns LP_EINVAL; wg_out may then be NULL).  Only for problems whose
+ * local multiply at rank k is the two-pass kernel, at the default work-item size.
+ * Z: device d x k FP64.  Synchronous. */
+lp_status lp_profile_local_multiply(lp_problem* P, int32_t k, const double* Z, double* wg_out,
+                                    int32_t max_wg, int32_t* n_wg);
+
 /* Batched orth: Q_b = orth(Y_b) for b < batch, each d x k FP64 (CholeskyQR2).
  *   Y, Q : device, batch * d * k FP64 (may alias);  flags: device int32[batch]
  *   or NULL, set to 1 where a Cholesky broke down.  Uses the problem's workspace and

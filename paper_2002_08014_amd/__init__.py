@@ -24,6 +24,7 @@ from ._lib import (  # noqa: F401
     lp_gram_disable,
     lp_eta,
     lp_local_multiply,
+    lp_profile_local_multiply,
     lp_orth,
     lp_orth_noalloc,
     lp_align,

@@ -24,7 +24,8 @@ MODES = {"vanilla": 0, "sign": 1, "opt": 2}
 
 EXPORTS = ("lp_strerror", "lp_last_error", "lp_workspace_size", "lp_create", "lp_destroy",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_run", "lp_solve", "lp_gram_bytes",
-           "lp_gram_enable", "lp_gram_disable", "lp_eta", "lp_local_multiply", "lp_orth", "lp_orth_noalloc",
+           "lp_gram_enable", "lp_gram_disable", "lp_eta", "lp_local_multiply", "lp_profile_local_multiply",
+           "lp_orth", "lp_orth_noalloc",
            "lp_align",
            "lp_sin_theta", "lp_sin_theta_r", "lp_generate", "lp_bandwidth_probe", "lp_copy_probe", "lp_server_footprint",
            "lp_server_create", "lp_server_submit", "lp_server_poll", "lp_server_wait",
@@ -173,6 +174,8 @@ def load() -> ctypes.CDLL:
                          ctypes.POINTER(RunStats)]
     L.lp_local_multiply.restype = i32
     L.lp_local_multiply.argtypes = [vp, i32, vp, vp]
+    L.lp_profile_local_multiply.restype = i32
+    L.lp_profile_local_multiply.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i32)]
     L.lp_orth.restype = i32
     L.lp_orth.argtypes = [vp, i32, i32, vp, vp, vp]
     L.lp_orth_noalloc.restype = i32
@@ -437,6 +440,20 @@ def lp_local_multiply(P: Problem, k: int, Z) -> torch.Tensor:
     Y = torch.empty(P.m, P.d, k, dtype=torch.float64, device=P.A.device)
     _check(L.lp_local_multiply(P.handle, k, _ptr(Zd), _ptr(Y)), "lp_local_multiply")
     return Y
+
+
+def lp_profile_local_multiply(P: Problem, k: int, Z) -> np.ndarray:
+    """Workgroup stamps of one two-pass local multiply: rows (pass, item, start us, end us)."""
+    L = load()
+    Zd = _dev_f64(Z, P.A.device)
+    n = ctypes.c_int32(0)
+    st = L.lp_profile_local_multiply(P.handle, k, _ptr(Zd), None, 0, ctypes.byref(n))
+    if n.value <= 0:
+        _check(st, "lp_profile_local_multiply")
+    out = np.zeros((n.value, 4), dtype=np.float64)
+    _check(L.lp_profile_local_multiply(P.handle, k, _ptr(Zd), out.ctypes.data, n.value, ctypes.byref(n)),
+           "lp_profile_local_multiply")
+    return out
 
 
 def lp_orth(P: Problem, Y: torch.Tensor):

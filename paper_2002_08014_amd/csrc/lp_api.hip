@@ -144,6 +144,11 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   L.rho = take(kHistCap * 8);
   L.rho_part = take(mb * 8);
   L.rho_ctr = take(4);
+  // start and end stamps of every workgroup of one two-pass local multiply at the
+  // default work-item size (pass 1: items x 128-row blocks, pass 2: items x
+  // 256-column blocks)
+  P->stamp_cap = (int64_t)P->items.size() * ((cr + 127) / 128 + (d + 255) / 256);
+  L.stamps = take((size_t)P->stamp_cap * 16);
   L.total = o;
   return true;
 }
@@ -1347,6 +1352,51 @@ lp_status lp_local_multiply(lp_problem* P, int32_t k, const double* Z, double* Y
   LP_HIP(launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part, q.items,
                                (int)P->plan.items.size(), P->stream));
   LP_HIP(launch_reduce_partials(P->plan, k, q.part, q.slot_off, Y_out, P->stream));
+  return join_out(P);
+}
+
+lp_status lp_profile_local_multiply(lp_problem* P, int32_t k, const double* Z, double* wg_out,
+                                     int32_t max_wg, int32_t* n_wg) {
+  if (P == nullptr || Z == nullptr || n_wg == nullptr || (wg_out == nullptr && max_wg > 0))
+    return fail(LP_EINVAL, "NULL argument");
+  lp_status st = check_k(P, k);
+  if (st != LP_OK) return st;
+  if (P->gram_on || fused_for_k(P, k) || !gemm_eligible(P->dtype, P->d, P->lda, P->A))
+    return fail(LP_EINVAL, "profiling covers the two-pass local multiply only");
+  const int64_t nitems = (int64_t)P->plan.items.size();
+  const int64_t g1 = nitems * ((P->plan.chunk_rows + 127) / 128);
+  const int64_t g2 = nitems * ((P->d + 255) / 256);
+  *n_wg = (int32_t)(g1 + g2);
+  if (g1 + g2 > P->plan.stamp_cap)
+    return fail(LP_EINVAL, "profile at the default work-item size (the stamp area is sized for it)");
+  if (max_wg < g1 + g2) return fail(LP_EINVAL, "wg_out holds fewer rows than *n_wg");
+  Ptrs q = ptrs(P);
+  if ((st = join_in(P)) != LP_OK) return st;
+  LP_HIP(launch_to_working(P->plan, 1, P->d, k, Z, q.Zw_shared, P->stream));
+  P->plan.stamps = (unsigned long long*)(P->ws + P->plan.L.stamps);
+  hipError_t e = launch_local_multiply(P->plan, P->A, P->lda, k, q.Zw_shared, 0, q.tbuf, q.part,
+                                       q.items, (int)nitems, P->stream);
+  P->plan.stamps = nullptr;
+  if (e != hipSuccess) return fail(LP_EDEVICE, std::string("profiled launch: ") + hipGetErrorString(e));
+  std::vector<unsigned long long> h((size_t)2 * (g1 + g2));
+  LP_HIP(hipMemcpyAsync(h.data(), P->ws + P->plan.L.stamps, h.size() * 8, hipMemcpyDeviceToHost,
+                        P->stream));
+  LP_HIP(hipStreamSynchronize(P->stream));
+  int khz = 0;
+  LP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, P->device));
+  if (khz <= 0) return fail(LP_EDEVICE, "wall clock rate unavailable");
+  unsigned long long t0 = h[0];
+  for (size_t j = 0; j < h.size(); j += 2) t0 = std::min(t0, h[j]);
+  const double us_per_tick = 1e3 / (double)khz;
+  for (int64_t wg = 0; wg < g1 + g2; ++wg) {
+    const bool second = wg >= g1;
+    const int64_t local = second ? wg - g1 : wg;
+    double* o = wg_out + 4 * wg;
+    o[0] = second ? 2.0 : 1.0;
+    o[1] = (double)(local % nitems);
+    o[2] = (double)(h[2 * wg] - t0) * us_per_tick;
+    o[3] = (double)(h[2 * wg + 1] - t0) * us_per_tick;
+  }
   return join_out(P);
 }
 

@@ -33,7 +33,7 @@ enum class LocalPath : int { TwoPass = 0, Mfma32 = 1, MfmaBf16 = 2 };
 struct Layout {
   // byte offsets into the workspace
   size_t Zi, Zw, Yi, tmp, Z, Zw_shared, Y, Uref, part, tbuf, gram, gram2, rinv, omat, sgn, flags,
-      items, slot_off, hist, ctr, scal, rho, rho_part, rho_ctr, total;
+      items, slot_off, hist, ctr, scal, rho, rho_part, rho_ctr, stamps, total;
 };
 
 constexpr int kHistCap = 1024;  // rounds of sin-theta history buffered on the device
@@ -55,6 +55,8 @@ struct Plan {
   bool split_operands;       // BF16 A: hi + lo BF16 operand pairs (FP32-class results)
   bool valu;                 // k <= 8: the fused vector-ALU kernel (off: two-pass kernel)
   int64_t min_chunk_rows;    // the default chunking the workspace was sized for
+  int64_t stamp_cap;         // workgroups of one two-pass local multiply the stamp area holds
+  unsigned long long* stamps = nullptr;   // set while a profiled launch is enqueued
   Layout L;
 };
 

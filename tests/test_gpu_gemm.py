@@ -91,3 +91,29 @@ def test_gemm_run_parity_k64(lp):
     r = lp.lp_run(P, 64, w.p_sched, "opt", w.Y0)
     ro = oracle.localpower(upcast(w.A), w.offsets, 64, w.p_sched, "opt", w.Y0)
     assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
+
+
+def test_profiled_local_multiply_stamps(lp):
+    """Workgroup stamps of one two-pass local multiply over uneven partitions: one
+    row per workgroup of both passes, ends after starts, items in range, and the
+    launch's partials still give the right product."""
+    w = synth.make_small(20000, 512, 40, 6, seed=8, dtype=torch.float32, uneven=True)
+    A_dev = w.A.to("cuda:0")
+    P = lp.lp_create(A_dev, w.offsets, 40)
+    Z = oracle.orth(np.random.default_rng(2).standard_normal((512, 40)))
+    st = lp.lp_profile_local_multiply(P, 40, Z)
+    cr = lp.lp_get_tuning(P)["chunk_rows"]
+    nitems = sum(-(-int(s) // cr) for s in np.diff(w.offsets))
+    g1, g2 = nitems * -(-cr // 128), nitems * -(-512 // 256)
+    assert st.shape == (g1 + g2, 4)
+    assert np.all(st[:g1, 0] == 1) and np.all(st[g1:, 0] == 2)
+    assert np.all((st[:, 1] >= 0) & (st[:, 1] < nitems))
+    assert np.all(st[:, 3] >= st[:, 2]) and st[:, 2].min() == 0.0
+    assert st[g1:, 2].min() >= st[:g1, 2].min()
+    Y = host(lp.lp_local_multiply(P, 40, torch.as_tensor(Z)))
+    A = upcast(A_dev)
+    Zw = Z.astype(np.float32).astype(np.float64)
+    for i in range(w.m):
+        Ai = A[w.offsets[i]:w.offsets[i + 1]]
+        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+        assert np.all(np.abs(Y[i] - Ai.T @ (Ai @ Zw)) <= (512 + Ai.shape[0]) * 2.0 ** -24 * bound)

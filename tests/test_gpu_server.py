@@ -127,3 +127,37 @@ def test_server_not_converged(lp, jobs):
     assert r["status"] == LP_ENOTCONV and r["rounds"] == 3
     Z = host(r["Z"])
     assert np.abs(Z.T @ Z - np.eye(w.k)).max() < 1e-10
+
+
+def test_server_bf16_fused_job_alone_and_in_a_mix(lp, jobs):
+    """A BF16 job on the fused BF16 kernel (k = 16, d = 1024, operand pairs) and a
+    BF16 job on the vector-ALU kernel (k = 8), both generated at admission, give
+    bitwise the same result alone and in a mix with the other jobs; both reach
+    the exact subspace."""
+    print("server: BF16 jobs alone vs mix", flush=True)
+    specs = [(32768, 1024, 16, 8, 501), (16384, 512, 8, 4, 502)]
+    alone = {}
+    for n, d, k, m, seed in specs:
+        S = lp.Server(hbm_budget_bytes=8 << 30, max_active=1)
+        S.submit(None, synth.equal_offsets(n, m), k, None, target=1e-5, max_rounds=300,
+                 gen=(n, d, torch.bfloat16, seed, 1.2, 0.97))
+        assert S.wait(1, timeout_s=120)
+        alone[seed] = S.poll()[0]
+        S.close()
+    S = lp.Server(hbm_budget_bytes=16 << 30, max_active=6)
+    ids = {}
+    for i, (w, mode, _) in enumerate(jobs):
+        _submit(S, w, mode, target=1e-5)
+        if i < len(specs):
+            n, d, k, m, seed = specs[i]
+            ids[S.submit(None, synth.equal_offsets(n, m), k, None, target=1e-5, max_rounds=300,
+                         gen=(n, d, torch.bfloat16, seed, 1.2, 0.97))] = (n, d, k, seed)
+    assert S.wait(len(jobs) + len(specs), timeout_s=180)
+    res = {r["id"]: r for r in S.poll()}
+    S.close()
+    for jid, (n, d, k, seed) in ids.items():
+        r, a = res[jid], alone[seed]
+        assert r["status"] == a["status"] == LP_OK
+        assert r["rounds"] == a["rounds"] and torch.equal(r["Z"], a["Z"])
+        _, U = lp.lp_generate(n, d, k, 1.2, 0.97, seed, dtype=None)
+        assert sin_theta_np(host(r["Z"]), host(U)) < 1e-4
