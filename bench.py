@@ -447,7 +447,17 @@ def measure(lp, synth, name, args, steps, warmup, headline=False):
     spec = WORKLOADS[name]
     dev = torch.device("cuda:0")
     log(f"generating {name} on the GPU")
-    w = getattr(synth, spec["gen"])(device=dev)
+    if headline and args.k:
+        # the same matrix at another rank; k <= 8 runs the fused vector-ALU kernel
+        w = getattr(synth, spec["gen"])(device=dev, k=args.k)
+        if args.k <= 8 and w.A.dtype in (torch.float32, torch.bfloat16):
+            # the committed counters are for k = 8
+            spec = dict(spec, sources=("k_valu.hip",), bound="hbm",
+                        traffic="local_multiply_valu_traffic.json" if args.k == 8 else None)
+        elif args.k != 16:
+            spec = dict(spec, traffic=None)
+    else:
+        w = getattr(synth, spec["gen"])(device=dev)
     modes = (args.mode,) if args.mode else spec["modes"]
     if args.rounds:
         w.p_sched = (list(w.p_sched) * args.rounds)[:args.rounds]
@@ -607,6 +617,8 @@ def main():
                     help="serving: Poisson arrival rates (jobs/s)")
     ap.add_argument("--rounds", type=int, default=0, help="override the workload's round count")
     ap.add_argument("--mode", default=None, choices=["sign", "opt", "vanilla"])
+    ap.add_argument("--k", type=int, default=0,
+                    help="run the workload's matrix at this rank (k <= 8: the vector-ALU kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-sub", action="store_true", help="default run: the headline workload only")
