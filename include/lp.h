@@ -115,6 +115,10 @@ lp_status lp_destroy(lp_problem* P);
  *                 fused vector-ALU kernel (A read once, FP32 arithmetic, no matrix
  *                 cores) unless local_kernel = 1 asks for the two-pass kernel.
  *                 Other shapes and ranks use the two-pass kernel.
+ *                 11: the two-pass kernel on BF16 matrix cores: every FP32 operand (A,
+ *                 Z_i, t) split exactly into three BF16 pieces and the six leading
+ *                 partial products summed in FP32 (dropped terms below 2^-23 of each
+ *                 product: FP32-class results); BF16 A needs three products.
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
  *                 default chosen at lp_create, which sized the workspace); 0 = default.
  *   cached_loads: 1 reads A with ordinary (cached) loads in the fused kernels; 0 (default)

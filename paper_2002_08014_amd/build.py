@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblp.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["lp_api.hip", "lp_server.hip", "k_local.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_valu.hip", "k_gemm.hip", "k_small.hip", "k_probe.hip", "k_diag.hip", "k_gen.hip", "lp_noalloc.hip"]
+SOURCES = ["lp_api.hip", "lp_server.hip", "k_local.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_valu.hip", "k_gemm.hip", "k_gemm3.hip", "k_small.hip", "k_probe.hip", "k_diag.hip", "k_gen.hip", "lp_noalloc.hip"]
 ARCH = "gfx950"
 
 

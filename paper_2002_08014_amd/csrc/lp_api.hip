@@ -180,7 +180,9 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
   if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A, P.split_operands))
     return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (gemm_eligible(P.dtype, P.d, lda, A))
-    return launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
+    return P.split_products
+               ? launch_local_multiply_gemm3(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s)
+               : launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
 }
 
@@ -791,8 +793,9 @@ lp_status lp_destroy(lp_problem* P) {
 lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   if (P == nullptr || t == nullptr || t->struct_size < (int32_t)sizeof(lp_tuning))
     return fail(LP_EINVAL, "problem/tuning is NULL or struct_size too small");
-  if (t->local_kernel < 0 || t->local_kernel > 10) return fail(LP_EINVAL, "local_kernel out of range");
-  if (t->local_kernel > 5 && fused_kind(P) == LocalPath::MfmaBf16)
+  if (t->local_kernel < 0 || t->local_kernel > 11) return fail(LP_EINVAL, "local_kernel out of range");
+  const bool two_pass = t->local_kernel == 1 || t->local_kernel == 11;
+  if (t->local_kernel > 5 && !two_pass && fused_kind(P) == LocalPath::MfmaBf16)
     return fail(LP_EINVAL, "the BF16 fused kernel has four variants (local_kernel 2 to 5)");
   int64_t cr = t->chunk_rows == 0 ? P->plan.min_chunk_rows : t->chunk_rows;
   if (cr % 16 != 0 || cr < P->plan.min_chunk_rows)
@@ -803,7 +806,7 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
   P->graphs.clear();
   const LocalPath fk = fused_kind(P);
-  if (t->local_kernel == 1 || (t->local_kernel >= 2 && fk == LocalPath::TwoPass)) {
+  if (two_pass || (t->local_kernel >= 2 && fk == LocalPath::TwoPass)) {
     P->plan.path = LocalPath::TwoPass;
   } else if (fk == LocalPath::Mfma32) {
     P->plan.path = fk;
@@ -817,7 +820,8 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   }
   P->plan.nt_loads = t->cached_loads == 0;
   P->plan.split_operands = t->split_operands != 0;
-  P->plan.valu = t->local_kernel != 1;
+  P->plan.valu = !two_pass;
+  P->plan.split_products = t->local_kernel == 11;
   build_items(&P->plan, P->offsets.data(), cr);
   return upload_items(P);
 }
@@ -825,7 +829,8 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
 lp_status lp_get_tuning(lp_problem* P, lp_tuning* t) {
   if (P == nullptr || t == nullptr) return fail(LP_EINVAL, "NULL argument");
   t->struct_size = sizeof(lp_tuning);
-  t->local_kernel = P->plan.path == LocalPath::TwoPass ? 1 : 2 + P->plan.variant;
+  t->local_kernel = P->plan.path == LocalPath::TwoPass ? (P->plan.split_products ? 11 : 1)
+                                                       : 2 + P->plan.variant;
   t->chunk_rows = P->plan.chunk_rows;
   t->cached_loads = P->plan.nt_loads ? 0 : 1;
   t->split_operands = P->plan.split_operands ? 1 : 0;
@@ -926,7 +931,7 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
       for (int lk = 2; lk <= lk_max; ++lk)
         for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, split});
     } else {
-      cand.push_back({(int32_t)sizeof(lp_tuning), 1, cr, 0, split});
+      for (int lk : {1, 11}) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, 0, split});
     }
   }
   if ((st = join_in(P)) != LP_OK) return st;
@@ -1364,8 +1369,10 @@ lp_status lp_profile_local_multiply(lp_problem* P, int32_t k, const double* Z, d
   if (P->gram_on || fused_for_k(P, k) || !gemm_eligible(P->dtype, P->d, P->lda, P->A))
     return fail(LP_EINVAL, "profiling covers the two-pass local multiply only");
   const int64_t nitems = (int64_t)P->plan.items.size();
-  const int64_t g1 = nitems * ((P->plan.chunk_rows + 127) / 128);
-  const int64_t g2 = nitems * ((P->d + 255) / 256);
+  int64_t rw1 = 0, cw2 = 0;
+  two_pass_geometry(P->plan, &rw1, &cw2);
+  const int64_t g1 = nitems * ((P->plan.chunk_rows + rw1 - 1) / rw1);
+  const int64_t g2 = nitems * ((P->d + cw2 - 1) / cw2);
   *n_wg = (int32_t)(g1 + g2);
   if (g1 + g2 > P->plan.stamp_cap)
     return fail(LP_EINVAL, "profile at the default work-item size (the stamp area is sized for it)");

@@ -54,6 +54,7 @@ struct Plan {
   bool nt_loads;             // nontemporal loads of A in the fused kernel
   bool split_operands;       // BF16 A: hi + lo BF16 operand pairs (FP32-class results)
   bool valu;                 // k <= 8: the fused vector-ALU kernel (off: two-pass kernel)
+  bool split_products = false;   // two-pass kernel on BF16 matrix cores (split operands)
   int64_t min_chunk_rows;    // the default chunking the workspace was sized for
   int64_t stamp_cap;         // workgroups of one two-pass local multiply the stamp area holds
   unsigned long long* stamps = nullptr;   // set while a profiled launch is enqueued
@@ -217,6 +218,17 @@ hipError_t launch_local_multiply_gemm(const Plan& P, const void* A, int64_t lda,
                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                       const WorkItem* items, int nitems,
                                       hipStream_t s);
+
+// The same two passes on BF16 matrix cores, every FP32 operand split exactly into three
+// BF16 pieces and the six leading partial products kept (FP32-class results; the
+// shapes and buffers of launch_local_multiply_gemm).
+hipError_t launch_local_multiply_gemm3(const Plan& P, const void* A, int64_t lda, int k,
+                                       const void* Zw, int64_t z_stride, void* tbuf, void* part,
+                                       const WorkItem* items, int nitems, hipStream_t s);
+
+// Rows per workgroup of pass 1 and columns per workgroup of pass 2 of the matrix-core
+// two-pass local multiply the plan selects (the workgroup stamps follow this order).
+void two_pass_geometry(const Plan& P, int64_t* rows_per_wg1, int64_t* cols_per_wg2);
 
 hipError_t launch_local_multiply_twopass(const Plan& P, const void* A, int64_t lda, int k,
                                          const void* Zw, int64_t z_stride, void* tbuf, void* part,

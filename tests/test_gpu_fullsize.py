@@ -197,13 +197,19 @@ def test_fp32_uneven_500000x4096_whole_run(lp):
     w = synth.make_fp32_uneven_500000x4096(device="cuda:0")
     assert w.mode == "opt" and list(w.p_sched) == [4] * 30 and w.m == 100
     P = lp.lp_create(w.A, w.offsets, w.k)
-    lp.lp_autotune(P, w.k)
+    tuned = lp.lp_autotune(P, w.k)
     r = _gpu_run(lp, P, w, list(w.p_sched), w.mode, "500000x4096 opt")
     assert r["stats"]["split_rounds"] == 1          # the benchmark's launch configuration
+    # the other form of the two-pass kernel (FP32 or split-BF16 matrix cores)
+    other = 1 if tuned["local_kernel"] == 11 else 11
+    lp.lp_set_tuning(P, other, tuned["chunk_rows"])
+    r2 = _gpu_run(lp, P, w, list(w.p_sched), w.mode, f"500000x4096 opt, local_kernel {other}")
     lp.lp_destroy(P)
     A = _host64(w.A)
     w.A = None
     torch.cuda.empty_cache()
     ro = _oracle_run(A, w, list(w.p_sched), w.mode, "500000x4096 opt")
-    _compare(r, ro, 1e-5, "500000x4096 opt")
-    assert r["stats"]["breakdowns"] == 0 and r["stats"]["near_singular"] == 0
+    _compare(r, ro, 1e-5, f"500000x4096 opt, local_kernel {tuned['local_kernel']}")
+    _compare(r2, ro, 1e-5, f"500000x4096 opt, local_kernel {other}")
+    for x in (r, r2):
+        assert x["stats"]["breakdowns"] == 0 and x["stats"]["near_singular"] == 0
