@@ -400,13 +400,15 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
-def load_balance(lp, w, k):
+def load_balance(lp, w, k, local_kernel=1):
     """How evenly one two-pass local multiply over the uneven partitions uses the
-    GPU, from per-workgroup start/end stamps (lp_profile_local_multiply, default
-    work-item size): workgroup busy times, the busy time per row of every
-    partition, and per pass the busy fraction of the launch (sum of busy times over
-    span x the largest number of workgroups seen running at once)."""
+    GPU, from per-workgroup start/end stamps (lp_profile_local_multiply, the
+    benchmark's kernel form at the default work-item size): workgroup busy times,
+    the busy time per row of every partition, and per pass the busy fraction of the
+    launch (sum of busy times over span x the largest number of workgroups seen
+    running at once)."""
     P = lp.lp_create(w.A, w.offsets, k)
+    lp.lp_set_tuning(P, local_kernel, 0)
     cr = lp.lp_get_tuning(P)["chunk_rows"]
     Z = np.linalg.qr(np.random.default_rng(0).standard_normal((w.d, k)))[0]
     st = lp.lp_profile_local_multiply(P, k, Z)
@@ -417,7 +419,8 @@ def load_balance(lp, w, k):
             item_part.append(i)
             item_rows.append(min(cr, int(w.offsets[i + 1]) - r))
     item_part, item_rows = np.array(item_part), np.array(item_rows)
-    out = {"work_item_rows": int(cr), "items": int(len(item_rows)), "workgroups": int(len(st))}
+    out = {"local_kernel": int(local_kernel), "work_item_rows": int(cr), "items": int(len(item_rows)),
+           "workgroups": int(len(st))}
     busy_part = np.zeros(w.m)
     for ps in (1, 2):
         sel = st[st[:, 0] == ps]
@@ -608,7 +611,7 @@ def measure(lp, synth, name, args, steps, warmup, headline=False):
         rec["trends"] = trends(lp, synth, w, k)
     if name == "fp32-uneven-500000x4096":
         log("load balance of the uneven partitions (workgroup stamps)")
-        rec["load_balance"] = load_balance(lp, w, k)
+        rec["load_balance"] = load_balance(lp, w, k, tuning["local_kernel"])
     if args.precision and name == "bf16-1048576x2048":
         rec["precision"] = precision_report(lp, synth, w, P, tuning, sched)
     if not args.no_cpu_baseline:
