@@ -453,13 +453,10 @@ def measure(lp, synth, name, args, steps, warmup, headline=False):
     dev = torch.device("cuda:0")
     log(f"generating {name} on the GPU")
     if headline and args.k:
-        # the same matrix at another rank; k <= 8 runs the fused vector-ALU kernel
+        # the same matrix at another rank (the counter record applies to k = 16 only;
+        # after autotuning, a k <= 8 run on the vector-ALU kernel takes its own)
         w = getattr(synth, spec["gen"])(device=dev, k=args.k)
-        if args.k <= 8 and w.A.dtype in (torch.float32, torch.bfloat16):
-            # the committed counters are for k = 8
-            spec = dict(spec, sources=("k_valu.hip",), bound="hbm",
-                        traffic="local_multiply_valu_traffic.json" if args.k == 8 else None)
-        elif args.k != 16:
+        if args.k != 16:
             spec = dict(spec, traffic=None)
     else:
         w = getattr(synth, spec["gen"])(device=dev)
@@ -473,6 +470,10 @@ def measure(lp, synth, name, args, steps, warmup, headline=False):
     tuning = lp.lp_autotune(P, k)
     log(f"chosen {tuning}")
     split_products = spec["bound"] == "mfma" and tuning["local_kernel"] == 11
+    if headline and args.k and args.k <= 8 and tuning["local_kernel"] == 0:
+        # the fused vector-ALU kernel (its committed counters are for k = 8)
+        spec = dict(spec, sources=("k_valu.hip",), bound="hbm",
+                    traffic="local_multiply_valu_traffic.json" if args.k == 8 else None)
     if split_products:
         # the two-pass kernel on BF16 matrix cores with exactly split FP32 operands
         spec = dict(spec, sources=("k_gemm3.hip",), traffic="local_multiply_gemm3_traffic.json")

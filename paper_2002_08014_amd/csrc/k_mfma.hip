@@ -1,4 +1,6 @@
-// Fused single-pass local multiply on CDNA4 matrix cores (FP32 A, k = 16).
+// Fused single-pass local multiply on CDNA4 matrix cores (FP32 A, k <= 16: a
+// rank below 16 runs the same 16-wide tiles with zero columns of Z_i, which
+// are not stored).
 //
 // Computes, for one work item (a contiguous row range of partition i),
 //   part = A_rows^T (A_rows Z_i)            (Eq. (power_yi) without 1/s_i)
@@ -41,7 +43,7 @@ __device__ inline f4 ldA(const float* p) {
 template <int NQ, int W, int OCC, int PF, bool NTL>
 __global__ void __launch_bounds__(64 * W, OCC)
 k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
-                int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+                int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr) {
   constexpr int NT = 64 * W;          // threads
   constexpr int D = 16 * NQ * W;      // columns of A
   constexpr int P = D + 4;            // padded LDS row (floats)
@@ -66,7 +68,7 @@ k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+    for (int c = 0; c < 4; ++c) zr[q][c] = i < kr ? Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * kr + i] : 0.f;
 
   f4 acc[NQ];
 #pragma unroll
@@ -148,11 +150,12 @@ k1_mfma_f32_k16(const float* __restrict__ A, int64_t lda, const float* __restric
     }
   }
   // acc[h][r] = Y[slice0 + NQ*(4g + r) + h][i]
-  float* o = part + (int64_t)it.slot * D * 16;
+  float* o = part + (int64_t)it.slot * D * kr;
 #pragma unroll
   for (int h = 0; h < NQ; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+    for (int r = 0; r < 4; ++r)
+      if (i < kr) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * kr + i] = acc[h][r];
 }
 
 // Software-pipelined form: two LDS tile buffers; in each step, product 2 of
@@ -162,7 +165,7 @@ template <int NQ, int W, bool NTL>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
                      int64_t z_stride, const WorkItem* __restrict__ items,
-                     float* __restrict__ part) {
+                     float* __restrict__ part, int kr) {
   constexpr int NT = 64 * W;
   constexpr int D = 16 * NQ * W;
   constexpr int P = D + 4;
@@ -186,7 +189,7 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+    for (int c = 0; c < 4; ++c) zr[q][c] = i < kr ? Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * kr + i] : 0.f;
   f4 acc[NQ];
 #pragma unroll
   for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
@@ -283,11 +286,12 @@ k1_mfma_f32_k16_pipe(const float* __restrict__ A, int64_t lda, const float* __re
       if (t + 3 < ntiles) load_tile(t + 3);
     }
   }
-  float* o = part + (int64_t)it.slot * D * 16;
+  float* o = part + (int64_t)it.slot * D * kr;
 #pragma unroll
   for (int h = 0; h < NQ; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+    for (int r = 0; r < 4; ++r)
+      if (i < kr) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * kr + i] = acc[h][r];
 }
 
 // Direct-to-LDS form: each wave copies its own column slice of every tile
@@ -342,7 +346,7 @@ __device__ inline void wait_vm_n() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N)
 template <int NQ, int W, int AUX>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
-                int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+                int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr) {
   constexpr int D = 16 * NQ * W;
   constexpr int S = 16 * NQ;            // columns per wave slice
   constexpr int RB = 4 * S;             // bytes per slice row
@@ -400,7 +404,7 @@ k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+    for (int c = 0; c < 4; ++c) zr[q][c] = i < kr ? Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * kr + i] : 0.f;
   f4 acc[NQ];
 #pragma unroll
   for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
@@ -455,11 +459,12 @@ k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restric
     }
     lds_barrier();   // every wave has read tpart before the next tile overwrites it
   }
-  float* o = part + (int64_t)it.slot * D * 16;
+  float* o = part + (int64_t)it.slot * D * kr;
 #pragma unroll
   for (int h = 0; h < NQ; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+    for (int r = 0; r < 4; ++r)
+      if (i < kr) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * kr + i] = acc[h][r];
 }
 
 // Software-pipelined direct-to-LDS form.  Per tile j: the operands of both
@@ -473,7 +478,7 @@ k1_mfma_f32_dma(const float* __restrict__ A, int64_t lda, const float* __restric
 template <int NQ, int W, int AUX>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_f32_dmap(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
-                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr) {
   constexpr int D = 16 * NQ * W;
   constexpr int S = 16 * NQ;            // columns per wave slice
   constexpr int RB = 4 * S;             // bytes per slice row
@@ -529,7 +534,7 @@ k1_mfma_f32_dmap(const float* __restrict__ A, int64_t lda, const float* __restri
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+    for (int c = 0; c < 4; ++c) zr[q][c] = i < kr ? Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * kr + i] : 0.f;
   f4 acc[NQ];
 #pragma unroll
   for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
@@ -602,11 +607,12 @@ k1_mfma_f32_dmap(const float* __restrict__ A, int64_t lda, const float* __restri
     tprev = t;
   }
   product2(a2p, tprev, 0, NQ);
-  float* o = part + (int64_t)it.slot * D * 16;
+  float* o = part + (int64_t)it.slot * D * kr;
 #pragma unroll
   for (int h = 0; h < NQ; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+    for (int r = 0; r < 4; ++r)
+      if (i < kr) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * kr + i] = acc[h][r];
 }
 
 // Direct-to-LDS form with two tiles in flight per wave.  Once a tile's
@@ -618,7 +624,7 @@ k1_mfma_f32_dmap(const float* __restrict__ A, int64_t lda, const float* __restri
 template <int NQ, int W, int AUX>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_f32_dma2(const float* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
-                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+                 int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr) {
   constexpr int D = 16 * NQ * W;
   constexpr int S = 16 * NQ;            // columns per wave slice
   constexpr int RB = 4 * S;             // bytes per slice row
@@ -673,7 +679,7 @@ k1_mfma_f32_dma2(const float* __restrict__ A, int64_t lda, const float* __restri
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) zr[q][c] = Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * 16 + i];
+    for (int c = 0; c < 4; ++c) zr[q][c] = i < kr ? Z[(int64_t)(slice0 + 16 * q + 4 * g + c) * kr + i] : 0.f;
   f4 acc[NQ];
 #pragma unroll
   for (int h = 0; h < NQ; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
@@ -740,18 +746,19 @@ k1_mfma_f32_dma2(const float* __restrict__ A, int64_t lda, const float* __restri
         acc[4 * cq + c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[st][c], t[s], acc[4 * cq + c], 0, 0, 0);
     }
   }
-  float* o = part + (int64_t)it.slot * D * 16;
+  float* o = part + (int64_t)it.slot * D * kr;
 #pragma unroll
   for (int h = 0; h < NQ; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * 16 + i] = acc[h][r];
+    for (int r = 0; r < 4; ++r)
+      if (i < kr) o[(int64_t)(slice0 + NQ * (4 * g + r) + h) * kr + i] = acc[h][r];
 }
 
 template <int NQ, int W, int AUX>
 hipError_t launch_dma2_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
-                          const WorkItem* items, float* o, hipStream_t s) {
+                          const WorkItem* items, float* o, int kr, hipStream_t s) {
   if constexpr (16 * NQ * W <= 1024 && NQ % 4 == 0) {
-    k1_mfma_f32_dma2<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_f32_dma2<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -760,21 +767,21 @@ hipError_t launch_dma2_nq(int nitems, const float* a, int64_t lda, const float* 
 
 template <int W, int AUX>
 hipError_t launch_f32_dma2(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
-                           int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                           int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   switch (d / (16 * W)) {
-    case 4: return launch_dma2_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 8: return launch_dma2_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 12: return launch_dma2_nq<12, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 16: return launch_dma2_nq<16, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 4: return launch_dma2_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 8: return launch_dma2_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 12: return launch_dma2_nq<12, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 16: return launch_dma2_nq<16, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int NQ, int W, int AUX>
 hipError_t launch_dmap_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
-                          const WorkItem* items, float* o, hipStream_t s) {
+                          const WorkItem* items, float* o, int kr, hipStream_t s) {
   if constexpr (16 * NQ * W <= 1024 && NQ % 4 == 0 && NQ <= 8) {
-    k1_mfma_f32_dmap<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_f32_dmap<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -783,19 +790,19 @@ hipError_t launch_dmap_nq(int nitems, const float* a, int64_t lda, const float* 
 
 template <int W, int AUX>
 hipError_t launch_f32_dmap(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
-                           int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                           int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   switch (d / (16 * W)) {
-    case 4: return launch_dmap_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 8: return launch_dmap_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 4: return launch_dmap_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 8: return launch_dmap_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int NQ, int W, int AUX>
 hipError_t launch_dma_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
-                         const WorkItem* items, float* o, hipStream_t s) {
+                         const WorkItem* items, float* o, int kr, hipStream_t s) {
   if constexpr (16 * NQ * W <= 1024 && NQ % 4 == 0) {
-    k1_mfma_f32_dma<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_f32_dma<NQ, W, AUX><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -804,21 +811,21 @@ hipError_t launch_dma_nq(int nitems, const float* a, int64_t lda, const float* z
 
 template <int W, int AUX>
 hipError_t launch_f32_dma(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
-                          int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                          int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   switch (d / (16 * W)) {
-    case 4: return launch_dma_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 8: return launch_dma_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 12: return launch_dma_nq<12, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
-    case 16: return launch_dma_nq<16, W, AUX>(nitems, a, lda, z, z_stride, items, o, s);
+    case 4: return launch_dma_nq<4, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 8: return launch_dma_nq<8, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 12: return launch_dma_nq<12, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 16: return launch_dma_nq<16, W, AUX>(nitems, a, lda, z, z_stride, items, o, kr, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int NQ, int W, bool NT>
 hipError_t launch_pipe_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
-                          const WorkItem* items, float* o, hipStream_t s) {
+                          const WorkItem* items, float* o, int kr, hipStream_t s) {
   if constexpr (16 * NQ * W <= 1024) {
-    k1_mfma_f32_k16_pipe<NQ, W, NT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_f32_k16_pipe<NQ, W, NT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -827,12 +834,12 @@ hipError_t launch_pipe_nq(int nitems, const float* a, int64_t lda, const float* 
 
 template <int W, bool NT>
 hipError_t launch_f32_pipe(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
-                           int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                           int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   switch (d / (16 * W)) {
-    case 4: return launch_pipe_nq<4, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
-    case 8: return launch_pipe_nq<8, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
-    case 12: return launch_pipe_nq<12, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
-    case 16: return launch_pipe_nq<16, W, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 4: return launch_pipe_nq<4, W, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 8: return launch_pipe_nq<8, W, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 12: return launch_pipe_nq<12, W, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 16: return launch_pipe_nq<16, W, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -842,9 +849,9 @@ hipError_t launch_f32_pipe(int64_t d, int nitems, const float* a, int64_t lda, c
 
 template <int NQ, int W, int OCC, int PF, bool NT>
 hipError_t launch_nq(int nitems, const float* a, int64_t lda, const float* z, int64_t z_stride,
-                     const WorkItem* items, float* o, hipStream_t s) {
+                     const WorkItem* items, float* o, int kr, hipStream_t s) {
   if constexpr (16 * NQ * W <= 1024) {
-    k1_mfma_f32_k16<NQ, W, OCC, PF, NT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_f32_k16<NQ, W, OCC, PF, NT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -853,18 +860,19 @@ hipError_t launch_nq(int nitems, const float* a, int64_t lda, const float* z, in
 
 template <int W, int OCC, int PF, bool NT>
 hipError_t launch_f32(int64_t d, int nitems, const float* a, int64_t lda, const float* z,
-                      int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                      int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   switch (d / (16 * W)) {
-    case 4: return launch_nq<4, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
-    case 8: return launch_nq<8, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
-    case 12: return launch_nq<12, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
-    case 16: return launch_nq<16, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, s);
+    case 4: return launch_nq<4, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 8: return launch_nq<8, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 12: return launch_nq<12, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 16: return launch_nq<16, W, OCC, PF, NT>(nitems, a, lda, z, z_stride, items, o, kr, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
-  return dtype == LP_F32 && k == 16 && (d == 256 || d == 512 || d == 768 || d == 1024) &&
+  // ranks below 16 run the k = 16 tiles with zero columns of Z (not stored)
+  return dtype == LP_F32 && k >= 1 && k <= 16 && (d == 256 || d == 512 || d == 768 || d == 1024) &&
          (lda % 4) == 0 && lda <= (int64_t(1) << 26);   // 32-bit in-tile load offsets
 }
 
@@ -875,47 +883,47 @@ bool mfma32_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k) {
 // flight per wave (8 waves at d = 1024, else 4).  The 8-wave forms need d in {512, 1024} (else 4 waves).
 template <bool NT>
 hipError_t dispatch_f32(const Plan& P, int nitems, const float* a, int64_t lda, const float* z,
-                        int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                        int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   const bool w8 = P.d == 512 || P.d == 1024;
   switch (P.variant) {
     case 1:
-      if (w8) return launch_f32<8, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (w8) return launch_f32<8, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+      return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     case 2:
-      if (w8) return launch_f32_pipe<8, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32_pipe<4, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-    case 3: return launch_f32_pipe<4, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (w8) return launch_f32_pipe<8, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+      return launch_f32_pipe<4, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+    case 3: return launch_f32_pipe<4, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     case 4:
-      if (w8) return launch_f32<8, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32<4, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (w8) return launch_f32<8, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+      return launch_f32<4, 1, 2, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     case 5: {
       // direct-to-LDS form: 8 waves when the slice is a whole number of 256-byte
       // groups (d = 512 gives 64-column slices: 4 waves), else 4 waves
       constexpr int AUX = NT ? 2 : 0;
-      if (P.d == 1024) return launch_f32_dma<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (P.d == 1024) return launch_f32_dma<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     }
     case 6: {
       // direct-to-LDS form with four waves (one per SIMD, 512 registers each)
       constexpr int AUX = NT ? 2 : 0;
-      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     }
     case 7: {
       // software-pipelined direct-to-LDS form with 64- or 128-column slices (eight
       // waves at d = 1024, four at d = 256 and 512); the plain form at d = 768
       constexpr int AUX = NT ? 2 : 0;
-      if (P.d == 1024) return launch_f32_dmap<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (P.d == 1024) return launch_f32_dmap<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
       if (P.d == 256 || P.d == 512)
-        return launch_f32_dmap<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+        return launch_f32_dmap<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+      return launch_f32_dma<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     }
     case 8: {
       // direct-to-LDS with two tiles in flight per wave (8 waves at d = 1024, else 4)
       constexpr int AUX = NT ? 2 : 0;
-      if (P.d == 1024) return launch_f32_dma2<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
-      return launch_f32_dma2<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+      if (P.d == 1024) return launch_f32_dma2<8, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
+      return launch_f32_dma2<4, AUX>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
     }
-    default: return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, s);
+    default: return launch_f32<4, 1, 1, NT>(P.d, nitems, a, lda, z, z_stride, items, o, kr, s);
   }
 }
 
@@ -926,8 +934,8 @@ hipError_t launch_local_multiply_mfma32(const Plan& P, const void* A, int64_t ld
   const float* a = (const float*)A;
   const float* z = (const float*)Zw;
   float* o = (float*)part;
-  if (P.nt_loads) return dispatch_f32<true>(P, nitems, a, lda, z, z_stride, items, o, s);
-  return dispatch_f32<false>(P, nitems, a, lda, z, z_stride, items, o, s);
+  if (P.nt_loads) return dispatch_f32<true>(P, nitems, a, lda, z, z_stride, items, o, k, s);
+  return dispatch_f32<false>(P, nitems, a, lda, z, z_stride, items, o, k, s);
 }
 
 }  // namespace lp

@@ -1,5 +1,6 @@
 // Fused single-pass local multiply on CDNA4 matrix cores for BF16 A
-// (k = 16 or 32, d in {512, 1024, 1536, 2048}).
+// (k <= 32, d in {512, 1024, 1536, 2048}; a rank below 16, or between 16 and
+// 32, runs the 16- or 32-wide tiles with zero columns of Z_i, not stored).
 //
 // Computes, for one work item (a contiguous row range of partition i),
 //   part = A_rows^T bf16(A_rows bf16(Z_i))      (Eq. (power_yi) without 1/s_i)
@@ -111,7 +112,7 @@ __device__ inline void wait_vm_n() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N)
 template <int W, int NC, int KT, int AUX, bool AHEAD, bool SPLIT>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
-             int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part) {
+             int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr) {
   constexpr int K = 16 * KT;
   constexpr int CW = 32 * NC;        // columns per wave slice
   constexpr int RB = 2 * CW;         // bytes of one slice row
@@ -162,7 +163,7 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float z = Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * K + 16 * kt + i];
+        const float z = 16 * kt + i < kr ? Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * kr + 16 * kt + i] : 0.f;
         zb[c][kt][e] = (__bf16)z;
         if constexpr (SPLIT) zl[c][kt][e] = (__bf16)(z - (float)zb[c][kt][e]);
       }
@@ -281,44 +282,44 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     }
   }
   // yacc[ct][kt][r] = Y[slice0 + 16ct + 4g + r][16kt + i]
-  float* o = part + (int64_t)it.slot * D * K;
+  float* o = part + (int64_t)it.slot * D * kr;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * K + 16 * kt + i] = yacc[ct][kt][r];
+        if (16 * kt + i < kr) o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * kr + 16 * kt + i] = yacc[ct][kt][r];
 }
 
 template <int W, int NC, int KT, bool AHEAD, bool SPLIT>
 hipError_t launch_nc(int nitems, bool nt, const uint16_t* a, int64_t lda, const float* z,
-                     int64_t z_stride, const WorkItem* items, float* o, hipStream_t s) {
+                     int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
   if (nt)
-    k1_mfma_bf16<W, NC, KT, 2, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_bf16<W, NC, KT, 2, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
   else
-    k1_mfma_bf16<W, NC, KT, 0, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o);
+    k1_mfma_bf16<W, NC, KT, 0, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
   return hipGetLastError();
 }
 
 template <int KT, bool AHEAD, bool SPLIT>
 hipError_t launch_kt_ahead(int64_t d, bool w8, int nitems, bool nt, const uint16_t* a, int64_t lda,
-                           const float* z, int64_t z_stride, const WorkItem* items, float* o,
+                           const float* z, int64_t z_stride, const WorkItem* items, float* o, int kr,
                            hipStream_t s) {
-  if (w8 && d == 1024) return launch_nc<8, 4, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+  if (w8 && d == 1024) return launch_nc<8, 4, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, kr, s);
   if constexpr (!(SPLIT && KT == 2)) {
-    if (w8 && d == 2048) return launch_nc<8, 8, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    if (w8 && d == 2048) return launch_nc<8, 8, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, kr, s);
   }
   switch (d) {
-    case 512: return launch_nc<4, 4, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 1024: return launch_nc<4, 8, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
-    case 1536: return launch_nc<4, 12, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+    case 512: return launch_nc<4, 4, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, kr, s);
+    case 1024: return launch_nc<4, 8, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, kr, s);
+    case 1536: return launch_nc<4, 12, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, kr, s);
     case 2048:
       // split operands at k = 32 need 2 (Z) + 1 (Y) x 256 registers per lane over the
       // slice of a 2048-wide row: more than one CU holds (the launcher's caller
       // routes that case to the two-pass kernel)
       if constexpr (SPLIT && KT == 2) return hipErrorInvalidValue;
-      else return launch_nc<4, 16, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, s);
+      else return launch_nc<4, 16, KT, AHEAD, SPLIT>(nitems, nt, a, lda, z, z_stride, items, o, kr, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -327,20 +328,20 @@ hipError_t launch_kt_ahead(int64_t d, bool w8, int nitems, bool nt, const uint16
 // 2, 3: the same with two tiles in flight per wave
 template <int KT, bool SPLIT>
 hipError_t launch_kt(int64_t d, int variant, int nitems, bool nt, const uint16_t* a, int64_t lda,
-                     const float* z, int64_t z_stride, const WorkItem* items, float* o,
+                     const float* z, int64_t z_stride, const WorkItem* items, float* o, int kr,
                      hipStream_t s) {
   const bool w8 = variant == 1 || variant == 3;
   if (variant >= 2)
-    return launch_kt_ahead<KT, true, SPLIT>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
-  return launch_kt_ahead<KT, false, SPLIT>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, s);
+    return launch_kt_ahead<KT, true, SPLIT>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, kr, s);
+  return launch_kt_ahead<KT, false, SPLIT>(d, w8, nitems, nt, a, lda, z, z_stride, items, o, kr, s);
 }
 
 }  // namespace
 
 bool mfma16_eligible(lp_dtype dtype, int64_t d, int64_t lda, int k, const void* A, bool split) {
-  return dtype == LP_BF16 && (k == 16 || k == 32) &&
+  return dtype == LP_BF16 && k >= 1 && k <= 32 &&
          (d == 512 || d == 1024 || d == 1536 || d == 2048) && (lda % 8) == 0 &&
-         ((uintptr_t)A % 16) == 0 && !(split && k == 32 && d == 2048);
+         ((uintptr_t)A % 16) == 0 && !(split && k > 16 && d == 2048);
 }
 
 hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t lda, int k,
@@ -350,12 +351,14 @@ hipError_t launch_local_multiply_mfma16(const Plan& P, const void* A, int64_t ld
   const uint16_t* a = (const uint16_t*)A;
   const float* z = (const float*)Zw;
   float* o = (float*)part;
+  // ranks below 16 (or between 16 and 32) run the 16- (32-) wide tiles with zero
+  // columns of Z_i, which are not stored
   if (P.split_operands) {
-    if (k == 32) return launch_kt<2, true>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
-    return launch_kt<1, true>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+    if (k > 16) return launch_kt<2, true>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, k, s);
+    return launch_kt<1, true>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, k, s);
   }
-  if (k == 32) return launch_kt<2, false>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
-  return launch_kt<1, false>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, s);
+  if (k > 16) return launch_kt<2, false>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, k, s);
+  return launch_kt<1, false>(P.d, P.variant, nitems, P.nt_loads, a, lda, z, z_stride, items, o, k, s);
 }
 
 }  // namespace lp

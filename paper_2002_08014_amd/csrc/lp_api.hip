@@ -554,8 +554,9 @@ hipError_t harvest_slots(lp_problem* P, std::vector<std::pair<int, int>>& pendin
 // Make the problem's own stream wait for the caller's stream.
 // The fused kernel family this problem can use (TwoPass when none applies).
 LocalPath fused_kind(const lp_problem* P) {
-  if (P->k_max >= 16 && mfma32_eligible(P->dtype, P->d, P->lda, 16)) return LocalPath::Mfma32;
-  if (P->k_max >= 16 && mfma16_eligible(P->dtype, P->d, P->lda, 16, P->A, false)) return LocalPath::MfmaBf16;
+  // the fused matrix-core kernels take every rank up to their tile width
+  if (mfma32_eligible(P->dtype, P->d, P->lda, 1)) return LocalPath::Mfma32;
+  if (mfma16_eligible(P->dtype, P->d, P->lda, 1, P->A, false)) return LocalPath::MfmaBf16;
   return LocalPath::TwoPass;
 }
 
@@ -820,7 +821,7 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   }
   P->plan.nt_loads = t->cached_loads == 0;
   P->plan.split_operands = t->split_operands != 0;
-  P->plan.valu = !two_pass;
+  P->plan.valu = t->local_kernel == 0;   // ranks <= 8: the vector-ALU kernel unless a kernel is named
   P->plan.split_products = t->local_kernel == 11;
   build_items(&P->plan, P->offsets.data(), cr);
   return upload_items(P);
@@ -917,17 +918,20 @@ lp_status lp_autotune(lp_problem* P, int32_t k, const char* cache_path, lp_tunin
     return LP_OK;
   }
   const int32_t split = P->plan.split_operands ? 1 : 0;   // kept: a choice of accuracy
-  const bool fused_ok = fused_for_k(P, k);
-  // k <= 8 on the vector-ALU kernel: only the work-item size varies (the matrix
-  // cores serve k >= 16)
-  const bool valu_k = P->plan.valu && valu_eligible(P->dtype, P->d, P->lda, k, P->A);
-  const int lk_max = fused_kind(P) == LocalPath::Mfma32 ? 10 : 5;
+  // candidates: the vector-ALU kernel (k <= 8), the fused matrix-core variants when
+  // they take this rank, else the two forms of the two-pass kernel; each at three
+  // work-item sizes
+  const bool valu_k = valu_eligible(P->dtype, P->d, P->lda, k, P->A);
+  const LocalPath fk = fused_kind(P);
+  const bool mfma_k =
+      (fk == LocalPath::Mfma32 && mfma32_eligible(P->dtype, P->d, P->lda, k)) ||
+      (fk == LocalPath::MfmaBf16 && mfma16_eligible(P->dtype, P->d, P->lda, k, P->A, split != 0));
+  const int lk_max = fk == LocalPath::Mfma32 ? 10 : 5;
   std::vector<lp_tuning> cand;
   const int64_t c0 = P->plan.min_chunk_rows;
   for (int64_t cr : {c0, 2 * c0, 4 * c0}) {
-    if (valu_k) {
-      cand.push_back({(int32_t)sizeof(lp_tuning), 0, cr, 0, split});
-    } else if (fused_ok) {
+    if (valu_k) cand.push_back({(int32_t)sizeof(lp_tuning), 0, cr, 0, split});
+    if (mfma_k) {
       for (int lk = 2; lk <= lk_max; ++lk)
         for (int cached = 0; cached <= 1; ++cached) cand.push_back({(int32_t)sizeof(lp_tuning), lk, cr, cached, split});
     } else {

@@ -1,6 +1,7 @@
-"""Parity of the fused matrix-core local multiply (FP32 A, k = 16) against the
-FP64 oracle, for every kernel variant, at small shapes with ragged tiles and at
-the full 262144 x 1024 benchmark shape (sampled partitions)."""
+"""Parity of the fused matrix-core local multiply (FP32 A, k <= 16) against the
+FP64 oracle, for every kernel variant, at small shapes with ragged tiles, at
+ranks below the tile width, and at the full 262144 x 1024 benchmark shape
+(sampled partitions)."""
 
 import numpy as np
 import pytest
@@ -50,14 +51,38 @@ def test_fused_small(lp, d, variant, cached):
     _check_partitions(Y, A, w.offsets, Z.astype(np.float32).astype(np.float64), range(m))
 
 
-def test_fused_other_k_falls_back(lp):
-    """k != 16 on a fused-eligible problem runs the generic kernel, still exact."""
-    w = synth.make_small(2048, 256, 8, 2, seed=1, dtype=torch.float32)
+@pytest.mark.parametrize("variant", [0, 2, 7, 9])
+@pytest.mark.parametrize("k", [1, 5, 8, 12, 15])
+@pytest.mark.parametrize("d", [256, 768])
+def test_fused_lower_ranks(lp, d, k, variant):
+    """Ranks below 16 run the k = 16 tiles with zero columns of Z, which are not
+    stored (local_kernel 0: the vector-ALU kernel where it applies, k <= 8 and d a
+    power of two, else the fused kernel); the same FP32 bound holds."""
+    print(f"fused lower rank d={d} k={k} variant={variant}", flush=True)
+    n, m = 3 * d + 37, 3
+    w = synth.make_small(n, d, k, m, seed=d + k, dtype=torch.float32, uneven=True)
     A_dev = w.A.to("cuda:0")
     P = lp.lp_create(A_dev, w.offsets, 16)
-    Z = oracle.orth(np.random.default_rng(2).standard_normal((256, 8)))
-    Y = host(lp.lp_local_multiply(P, 8, torch.as_tensor(Z)))
-    _check_partitions(Y, upcast(A_dev), w.offsets, Z.astype(np.float32).astype(np.float64), range(2))
+    lp.lp_set_tuning(P, variant, 0)
+    Z = oracle.orth(np.random.default_rng(d + k).standard_normal((d, k)))
+    Y = host(lp.lp_local_multiply(P, k, torch.as_tensor(Z)))
+    assert Y.shape == (m, d, k)
+    _check_partitions(Y, upcast(A_dev), w.offsets, Z.astype(np.float32).astype(np.float64), range(m))
+
+
+def test_fused_rank12_run_parity(lp):
+    """Rounds of p = 4 at k = 12 through the fused kernel (zero-padded tiles):
+    within 1e-5 of the oracle, sign decisions equal."""
+    print("fused run k=12", flush=True)
+    w = synth.make_small(16384, 512, 12, 4, seed=31, dtype=torch.float32, gap=1.3, p_sched=[4] * 6,
+                         device="cuda:0")
+    P = lp.lp_create(w.A, w.offsets, 12)
+    lp.lp_set_tuning(P, 9, 0)
+    r = lp.lp_run(P, 12, w.p_sched, "sign", w.Y0, record_signs=True)
+    ro = oracle.localpower(upcast(w.A), w.offsets, 12, w.p_sched, "sign", w.Y0)
+    assert sin_theta_np(host(r["Z"]), ro["Z"]) < 1e-5
+    assert ro["ambiguous"] == 0
+    assert np.array_equal(r["signs"], np.stack(ro["signs"]))
 
 
 @pytest.fixture(scope="module")

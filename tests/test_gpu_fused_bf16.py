@@ -1,4 +1,4 @@
-"""Parity of the fused BF16 matrix-core local multiply (BF16 A, k = 16 or 32)
+"""Parity of the fused BF16 matrix-core local multiply (BF16 A, k <= 32)
 against the FP64 oracle: small shapes with ragged tiles for every width, k and
 variant, the full 1048576 x 2048 precision-form shape on sampled partitions,
 and whole runs.
@@ -68,20 +68,22 @@ def test_bf16_fused_rejects_extra_variants(lp):
         lp.lp_set_tuning(P, 6, 0)
 
 
-def test_bf16_other_k_falls_back(lp):
-    """k outside {16, 32} on a fused-eligible BF16 problem runs the generic
-    kernel (FP32 operands), which meets the FP32 bound."""
-    w = synth.make_small(2048, 512, 8, 2, seed=2, dtype=torch.bfloat16)
+@pytest.mark.parametrize("variant", [2, 5])
+@pytest.mark.parametrize("k", [3, 8, 12, 20, 31])
+@pytest.mark.parametrize("d", [512, 1536])
+def test_bf16_fused_other_ranks(lp, d, k, variant):
+    """Ranks below 16, or between 16 and 32, run the 16- or 32-wide tiles with
+    zero columns of Z (not stored); the BF16-operand bound holds."""
+    print(f"bf16 fused rank d={d} k={k} variant={variant}", flush=True)
+    n, m = 3 * d + 37, 3
+    w = synth.make_small(n, d, k, m, seed=d + k + 5, dtype=torch.bfloat16, uneven=True)
     A_dev = w.A.to("cuda:0")
     P = lp.lp_create(A_dev, w.offsets, 32)
-    Z = oracle.orth(np.random.default_rng(3).standard_normal((512, 8)))
-    Y = host(lp.lp_local_multiply(P, 8, torch.as_tensor(Z)))
-    A = upcast(A_dev)
-    Zw = Z.astype(np.float32).astype(np.float64)
-    for i in range(2):
-        Ai = A[w.offsets[i]:w.offsets[i + 1]]
-        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
-        assert np.all(np.abs(Y[i] - Ai.T @ (Ai @ Zw)) <= (512 + Ai.shape[0]) * U_32 * bound)
+    lp.lp_set_tuning(P, variant, 0)
+    Z = oracle.orth(np.random.default_rng(d + k + 5).standard_normal((d, k)))
+    Y = host(lp.lp_local_multiply(P, k, torch.as_tensor(Z)))
+    assert Y.shape == (m, d, k)
+    _check(Y, upcast(A_dev), w.offsets, Z.astype(np.float32).astype(np.float64), range(m))
 
 
 @pytest.fixture(scope="module")
@@ -151,7 +153,7 @@ def _check_split(Y, A, offsets, Zw, parts):
 
 
 @pytest.mark.parametrize("variant", [2, 3, 4, 5])
-@pytest.mark.parametrize("k", [16, 32])
+@pytest.mark.parametrize("k", [5, 16, 24, 32])
 @pytest.mark.parametrize("d", [512, 1024, 1536, 2048])
 def test_bf16_split_operands_small(lp, d, k, variant):
     print(f"bf16 split operands d={d} k={k} variant={variant}", flush=True)
@@ -164,7 +166,7 @@ def test_bf16_split_operands_small(lp, d, k, variant):
     Z = oracle.orth(np.random.default_rng(d + k + 1).standard_normal((d, k)))
     Y = host(lp.lp_local_multiply(P, k, torch.as_tensor(Z)))
     Zw = Z.astype(np.float32).astype(np.float64)
-    if k == 32 and d == 2048:
+    if k > 16 and d == 2048:
         # the pairs do not fit: the two-pass kernel with FP32 operands runs
         for i in range(m):
             Ai = upcast(A_dev)[w.offsets[i]:w.offsets[i + 1]]
