@@ -98,7 +98,8 @@ lp_status lp_destroy(lp_problem* P);
  *   local_kernel: 0 automatic; 1 two-pass kernel (t = A Z, then A^T t; FP32 matrix cores
  *                 for FP32/BF16 A, FP64 arithmetic for FP64 A).  Fused matrix-core kernels
  *                 (A read once), one workgroup per CU:
- *                 FP32 A (k = 16, d in {256, 512, 768, 1024}): 2 four waves; 3 eight waves;
+ *                 FP32 A (k <= 16, d in {256, 512, 768, 1024}; a rank below 16 runs the
+ *                 16-wide tiles with zero columns of Z): 2 four waves; 3 eight waves;
  *                 4 software-pipelined (two LDS tiles, product 2 of one tile interleaved with
  *                 product 1 of the next), eight waves; 5 pipelined, four waves; 6 eight
  *                 waves with the next two tiles in flight (deeper prefetch); 7 direct-to-LDS
@@ -108,12 +109,13 @@ lp_status lp_destroy(lp_problem* P);
  *                 else four); 10 direct-to-LDS with two tiles in flight per wave (eight
  *                 waves at d = 1024, else four).  The eight-wave forms need d in {512, 1024} (else they run
  *                 with four waves).
- *                 BF16 A (k in {16, 32}, d in {512, 1024, 1536, 2048}; Z and t rounded to
- *                 BF16 as operands): 2 four waves; 3 eight waves (d in {1024, 2048});
+ *                 BF16 A (k <= 32, d in {512, 1024, 1536, 2048}, the 16- or 32-wide tiles
+ *                 padded likewise; Z and t rounded to BF16 as operands): 2 four waves;
+ *                 3 eight waves (d in {1024, 2048});
  *                 4 and 5 the same with two tiles in flight per wave.
- *                 Ranks k <= 8 (FP32 or BF16 A, d a power of two in [256, 4096]) run a
- *                 fused vector-ALU kernel (A read once, FP32 arithmetic, no matrix
- *                 cores) unless local_kernel = 1 asks for the two-pass kernel.
+ *                 With local_kernel 0, ranks k <= 8 (FP32 or BF16 A, d a power of two in
+ *                 [256, 4096]) run a fused vector-ALU kernel (A read once, FP32
+ *                 arithmetic, no matrix cores); naming a kernel (1..11) runs that one.
  *                 Other shapes and ranks use the two-pass kernel.
  *                 11: the two-pass kernel on BF16 matrix cores: every FP32 operand (A,
  *                 Z_i, t) split exactly into three BF16 pieces and the six leading
@@ -127,7 +129,7 @@ lp_status lp_destroy(lp_problem* P);
  *                 t = A Z once to BF16 (a sin theta floor near 1e-3 against FP64 on the
  *                 same values, within the BF16 tolerance of 2e-2).  1: each operand is a
  *                 pair hi = bf16(x), lo = bf16(x - hi) and every product is taken twice,
- *                 FP32-class results for twice the matrix-core work; at k = 32, d = 2048
+ *                 FP32-class results for twice the matrix-core work; at k > 16, d = 2048
  *                 (the pairs do not fit a CU's registers) the two-pass kernel with FP32
  *                 operands runs instead.  The autotuner keeps this setting. */
 typedef struct {
