@@ -120,7 +120,9 @@ lp_status lp_destroy(lp_problem* P);
  *                 11: the two-pass kernel on BF16 matrix cores: every FP32 operand (A,
  *                 Z_i, t) split exactly into three BF16 pieces and the six leading
  *                 partial products summed in FP32 (dropped terms below 2^-23 of each
- *                 product: FP32-class results); BF16 A needs three products.
+ *                 product: FP32-class results); BF16 A needs three products.  With
+ *                 local_kernel 0 the two-pass shapes run this form for BF16 A and for
+ *                 k > 16, the FP32-matrix-core form (1) otherwise.
  *   chunk_rows  : rows of A per workgroup work item (a multiple of 16, at least the
  *                 default chosen at lp_create, which sized the workspace); 0 = default.
  *   cached_loads: 1 reads A with ordinary (cached) loads in the fused kernels; 0 (default)

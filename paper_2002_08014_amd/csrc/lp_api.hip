@@ -179,10 +179,13 @@ hipError_t launch_local_multiply(const Plan& P, const void* A, int64_t lda, int 
     return launch_local_multiply_mfma32(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
   if (P.path == LocalPath::MfmaBf16 && mfma16_eligible(P.dtype, P.d, lda, k, A, P.split_operands))
     return launch_local_multiply_mfma16(P, A, lda, k, Zw, z_stride, part, items_dev, nitems, s);
-  if (gemm_eligible(P.dtype, P.d, lda, A))
-    return P.split_products
-               ? launch_local_multiply_gemm3(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s)
-               : launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
+  if (gemm_eligible(P.dtype, P.d, lda, A)) {
+    // without a named kernel: split operands on BF16 matrix cores for BF16 A (three
+    // BF16 products, exact) and for k > 16 (where FP32 matrix cores bind)
+    const bool split = P.split_products || (P.two_pass_auto && (P.dtype == LP_BF16 || k > 16));
+    return split ? launch_local_multiply_gemm3(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s)
+                 : launch_local_multiply_gemm(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
+  }
   return launch_local_multiply_twopass(P, A, lda, k, Zw, z_stride, tbuf, part, items_dev, nitems, s);
 }
 
@@ -823,6 +826,7 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
   P->plan.split_operands = t->split_operands != 0;
   P->plan.valu = t->local_kernel == 0;   // ranks <= 8: the vector-ALU kernel unless a kernel is named
   P->plan.split_products = t->local_kernel == 11;
+  P->plan.two_pass_auto = t->local_kernel == 0;
   build_items(&P->plan, P->offsets.data(), cr);
   return upload_items(P);
 }

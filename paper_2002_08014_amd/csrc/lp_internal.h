@@ -55,6 +55,7 @@ struct Plan {
   bool split_operands;       // BF16 A: hi + lo BF16 operand pairs (FP32-class results)
   bool valu;                 // k <= 8: the fused vector-ALU kernel (off: two-pass kernel)
   bool split_products = false;   // two-pass kernel on BF16 matrix cores (split operands)
+  bool two_pass_auto = true;      // no kernel named: the two-pass form is chosen per launch
   int64_t min_chunk_rows;    // the default chunking the workspace was sized for
   int64_t stamp_cap;         // workgroups of one two-pass local multiply the stamp area holds
   unsigned long long* stamps = nullptr;   // set while a profiled launch is enqueued
