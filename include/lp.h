@@ -25,8 +25,9 @@
  *     local-Gram form and eta, in the buffer passed to lp_gram_enable);
  *     lp_sin_theta uses one of 64 result cells the library holds in static
  *     device memory.  The serving layer (lp_server_*) is the exception: it
- *     allocates each admitted job's footprint with stream-ordered allocation
- *     (hipMallocAsync) and frees it when the job ends, and pinned host cells.
+ *     allocates one device arena of its budget at lp_server_create (freed by
+ *     lp_server_destroy) and places each admitted job's footprint in a free
+ *     range of it; plus pinned host cells.
  *   - All GPU work is enqueued on the stream given to lp_create (a hipStream_t;
  *     NULL means the legacy default stream); calls that return host results
  *     synchronise that stream before returning.
@@ -498,7 +499,10 @@ typedef struct {
 lp_status lp_server_footprint(const lp_job* job, size_t* bytes);
 
 /* Create a server on the current HIP device with a device-memory budget and at
- * most max_active (1..64) jobs admitted at once; starts its worker thread. */
+ * most max_active (1..64) jobs admitted at once; allocates the budget as one
+ * device arena (LP_ENOMEM when it does not fit in free device memory) and starts
+ * its worker thread.  Jobs are admitted in submission order when a contiguous
+ * range of their footprint is free in the arena. */
 lp_status lp_server_create(lp_server** out, size_t hbm_budget_bytes, int32_t max_active);
 
 /* Queue a job (non-blocking).  LP_EINVAL for an invalid job, LP_ENOMEM when its

@@ -109,11 +109,14 @@ __device__ inline void wait_vm_n() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N)
 // blocks (k = 16 KT); AUX: cache policy of the A loads (0 default, 2 nontemporal);
 // AHEAD: two tiles in flight per wave (a buffer is refilled with the tile two
 // ahead as soon as this wave's last read of it is done) instead of one.
-template <int W, int NC, int KT, int AUX, bool AHEAD, bool SPLIT>
+template <int W, int NC, int KT, int AUX, bool AHEAD, bool SPLIT, bool FULL>
 __global__ void __launch_bounds__(64 * W, 1)
 k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restrict__ Zw,
-             int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr) {
+             int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ part, int kr_in) {
   constexpr int K = 16 * KT;
+  // FULL: the rank is the tile width (a compile-time stride and no column tests:
+  // at d = 2048, k = 32 the register file is full and a run-time rank spills)
+  const int kr = FULL ? K : kr_in;
   constexpr int CW = 32 * NC;        // columns per wave slice
   constexpr int RB = 2 * CW;         // bytes of one slice row
   constexpr int TB = kRows * RB;     // bytes of one wave tile
@@ -163,7 +166,7 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float z = 16 * kt + i < kr ? Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * kr + 16 * kt + i] : 0.f;
+        const float z = (FULL || 16 * kt + i < kr) ? Z[(int64_t)(slice0 + 32 * c + 8 * g + e) * kr + 16 * kt + i] : 0.f;
         zb[c][kt][e] = (__bf16)z;
         if constexpr (SPLIT) zl[c][kt][e] = (__bf16)(z - (float)zb[c][kt][e]);
       }
@@ -289,16 +292,21 @@ k1_mfma_bf16(const uint16_t* __restrict__ A, int64_t lda, const float* __restric
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (16 * kt + i < kr) o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * kr + 16 * kt + i] = yacc[ct][kt][r];
+        if (FULL || 16 * kt + i < kr) o[(int64_t)(slice0 + 16 * ct + 4 * g + r) * kr + 16 * kt + i] = yacc[ct][kt][r];
 }
 
 template <int W, int NC, int KT, bool AHEAD, bool SPLIT>
 hipError_t launch_nc(int nitems, bool nt, const uint16_t* a, int64_t lda, const float* z,
                      int64_t z_stride, const WorkItem* items, float* o, int kr, hipStream_t s) {
-  if (nt)
-    k1_mfma_bf16<W, NC, KT, 2, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
+  const bool full = kr == 16 * KT;
+  if (nt && full)
+    k1_mfma_bf16<W, NC, KT, 2, AHEAD, SPLIT, true><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
+  else if (nt)
+    k1_mfma_bf16<W, NC, KT, 2, AHEAD, SPLIT, false><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
+  else if (full)
+    k1_mfma_bf16<W, NC, KT, 0, AHEAD, SPLIT, true><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
   else
-    k1_mfma_bf16<W, NC, KT, 0, AHEAD, SPLIT><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
+    k1_mfma_bf16<W, NC, KT, 0, AHEAD, SPLIT, false><<<nitems, 64 * W, 0, s>>>(a, lda, z, z_stride, items, o, kr);
   return hipGetLastError();
 }
 

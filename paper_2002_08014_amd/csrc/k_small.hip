@@ -692,6 +692,63 @@ __device__ inline void sym_schur2(double app, double aqq, double apq, double* c,
   *s = t * (*c);
 }
 
+// Largest eigenvalue of the symmetric positive semidefinite k x k matrix G in
+// the LDS array A (overwritten; B is LDS scratch of the same size), by repeated
+// squaring: A_0 = G / s_0 and A_i = A_{i-1}^2 / s_i, with s_i the trace that
+// gives A_i trace one.  Then tr(G^(2^j)) = prod_{i <= j} s_i^(2^(j-i)), and
+//   lambda_max <= (tr G^(2^j))^(2^-j) = s_0 s_1^(1/2) ... s_j^(2^-j)
+//              <= mult^(2^-j) lambda_max,
+// mult being the number of eigenvalues that survive the squarings next to
+// lambda_max (at most k = 64).  48 squarings bound the overestimate by
+// 64^(2^-48) - 1 < 1.5e-14; the squaring stops early once a trace is one to
+// rounding (A is then a rank-one projector and every later s_i is one).  The
+// product is evaluated as s_0 sqrt(s_1 sqrt(s_2 ...)) from the innermost
+// factor.  Each rounding error enters with weight 2^-i, so the relative error
+// stays a few ulps.  A zero trace gives 0 and a NaN trace NaN.  Every thread
+// gets the value.  A^2 = A^T A is the Gram tile of A with itself (A symmetric).
+constexpr int kSquarings = 48;
+
+template <int KC>
+__device__ double lam_max_psd(double* A, double* B, int k) {
+  __shared__ double sv[kSquarings + 1];
+  const int kk = k * k;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int j = 0; j < k; ++j) t += A[j * k + j];
+    sv[0] = t;
+  }
+  __syncthreads();
+  const double s0 = sv[0];
+  if (s0 != s0) return s0;
+  if (!(s0 > 0.0)) return 0.0;
+  for (int e = threadIdx.x; e < kk; e += kBlock) A[e] /= s0;
+  __syncthreads();
+  double* cur = A;
+  double* nxt = B;
+  int last = 0;
+  for (int i = 1; i <= kSquarings; ++i) {
+    gram_tile<KC>(cur, cur, k, k, nxt);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int j = 0; j < k; ++j) t += nxt[j * k + j];
+      sv[i] = t;
+    }
+    __syncthreads();
+    const double s = sv[i];
+    for (int e = threadIdx.x; e < kk; e += kBlock) nxt[e] /= s;
+    __syncthreads();
+    double* sw = cur;
+    cur = nxt;
+    nxt = sw;
+    last = i;
+    if (fabs(s - 1.0) <= 4.0 * 2.220446049250313e-16) break;
+  }
+  double t = sv[last];
+  for (int q = last - 1; q >= 1; --q) t = sv[q] * sqrt(t);
+  return last >= 1 ? s0 * sqrt(t) : s0;
+}
+
 // Parallel cyclic Jacobi on the symmetric k x k LDS matrix S; V (k x k, LDS,
 // may be NULL) accumulates the rotations.  On exit diag(S) holds eigenvalues.
 __device__ void jacobi_sym_lds(double* S, double* V, int k, double* cs, double* sn, int* flag) {
@@ -699,17 +756,29 @@ __device__ void jacobi_sym_lds(double* S, double* V, int k, double* cs, double* 
   const int npairs = kk / 2;
   if (V != nullptr)
     for (int e = threadIdx.x; e < k * k; e += blockDim.x) V[e] = (e / k == e % k) ? 1.0 : 0.0;
+  __shared__ double roff[kBlock], rtot[kBlock];
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
-    // convergence test on the off-diagonal mass
-    if (threadIdx.x == 0) {
+    // convergence test on the off-diagonal mass (per-thread sums, then a tree
+    // in a fixed order; the launch has kBlock threads)
+    {
       double off = 0.0, tot = 0.0;
-      for (int e = 0; e < k * k; ++e) {
+      for (int e = threadIdx.x; e < k * k; e += kBlock) {
         const double v = S[e] * S[e];
         tot += v;
         if (e / k != e % k) off += v;
       }
-      *flag = (off <= 1e-30 * tot) ? 1 : 0;
+      roff[threadIdx.x] = off;
+      rtot[threadIdx.x] = tot;
+      __syncthreads();
+      for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+          roff[threadIdx.x] += roff[threadIdx.x + h];
+          rtot[threadIdx.x] += rtot[threadIdx.x + h];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) *flag = (roff[0] <= 1e-30 * rtot[0]) ? 1 : 0;
     }
     __syncthreads();
     if (*flag) break;
@@ -915,8 +984,6 @@ sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Zs, int64_t
   __shared__ double C[kMaxK * kMaxK];
   __shared__ double G[kMaxK * kMaxK];
   __shared__ double Wt[16 * kMaxK];
-  __shared__ double cs[kMaxK / 2 + 1], sn[kMaxK / 2 + 1];
-  __shared__ int flag;
   const int kk = k * k;
   // C = Z^T U (r x k)
   for (int e = threadIdx.x; e < (diff ? 0 : r * k); e += blockDim.x) {
@@ -961,12 +1028,142 @@ sin_theta_kernel(int64_t d, int r, int k, const double* __restrict__ Zs, int64_t
     if (e < kk) G[e] = g[q];
   }
   __syncthreads();
-  jacobi_sym_lds(G, nullptr, k, cs, sn, &flag);
+  const double lam = lam_max_psd<kMaxK / 16>(G, C, k);   // C is free again
   if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < k; ++j) mx = fmax(mx, G[j * k + j]);
-    const double v = sqrt(fmax(mx, 0.0));
+    const double v = sqrt(fmax(lam, 0.0));
     if (out != nullptr) out[blockIdx.x] = v;
+    if (hist != nullptr) {
+      hist[*ctr] = v;
+      *ctr = *ctr + 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same sin theta_k(Z, U) over many workgroups (the per-round form): the
+// O(d r k) products run per 64-row chunk and only the k x k eigenvalue problem
+// runs in one workgroup.
+//   1. partial C_c = Z_c^T U_c per chunk            (sin_cross_kernel)
+//   2. C = sum_c C_c                                  (sum_gram_kernel)
+//   3. W_c = U_c - Z_c C, partial G_c = W_c^T W_c     (sin_resid_kernel)
+//   4. G = sum_c G_c                                  (sum_gram_kernel)
+//   5. sqrt(lambda_max(G))                            (sin_eig_kernel)
+// ---------------------------------------------------------------------------
+
+// out[i][j] = sum_{q < rows} Xs[q][i] Ws[q][j] (i < rx, j < kw; row strides rx
+// and kw <= 16 KC) on FP64 matrix cores: wave w owns the 16 x 16 output blocks
+// w, w + 4, ...; K = rows in steps of 4 with A[i][q] = X[r + q][16 bi + i] and
+// B[q][j] = W[r + q][16 bj + j].
+template <int KC>
+__device__ void cross_tile(const double* Xs, int rx, const double* Ws, int kw, int rows,
+                           double* out) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = lane & 15, q = lane >> 4;
+  const int bx = (rx + 15) / 16, bw = (kw + 15) / 16;
+  for (int blk = w; blk < bx * bw; blk += 4) {
+    const int bi = blk / bw, bj = blk - (blk / bw) * bw;
+    const int ci = 16 * bi + c, cj = 16 * bj + c;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < rows; r += 4) {
+      const int rr = r + q;
+      const double a = (rr < rows && ci < rx) ? Xs[rr * rx + ci] : 0.0;
+      const double b = (rr < rows && cj < kw) ? Ws[rr * kw + cj] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    // lane l holds entries (16 bi + 4t + l/16, 16 bj + l%16)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = 16 * bi + 4 * t + q, j = cj;
+      if (i < rx && j < kw) out[i * kw + j] = acc[t];
+    }
+  }
+}
+
+// grid (ceil(d / 64)): part[c] = Z_c^T U_c (r x k) of the 64-row chunk c.
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+sin_cross_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
+                 const double* __restrict__ U, double* __restrict__ part) {
+  __shared__ double zs[kGramRows * kMaxK];
+  __shared__ double us[kGramRows * kMaxK];
+  const int c = blockIdx.x;
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  load_tile<4 * KC>(Z + r0 * r, rows * r, zs);
+  load_tile<4 * KC>(U + r0 * k, rows * k, us);
+  __syncthreads();
+  cross_tile<KC>(zs, r, us, k, rows, part + (int64_t)c * r * k);
+}
+
+// grid (ceil(d / 64)): W_c = U_c - Z_c C for the 64-row chunk c and its Gram
+// partial gpart[c] = W_c^T W_c (k x k).  The product runs on FP64 matrix cores
+// with the accumulators started at U_c: wave w owns rows 16w..16w+15, lane l,
+// block bj, t holds W entry (16w + 4t + l/16, 16 bj + l%16).
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+sin_resid_kernel(int64_t d, int r, int k, const double* __restrict__ Z,
+                 const double* __restrict__ U, const double* __restrict__ C,
+                 double* __restrict__ gpart) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  __shared__ double cm[kMaxK * kMaxK];
+  __shared__ double zs[kGramRows * kMaxK];
+  __shared__ double ws[kGramRows * kMaxK];
+  const int c = blockIdx.x;
+  const int64_t r0 = (int64_t)c * kGramRows;
+  const int rows = (int)min<int64_t>(kGramRows, d - r0);
+  load_tile<KC * KC>(C, r * k, cm);
+  load_tile<4 * KC>(Z + r0 * r, rows * r, zs);
+  load_tile<4 * KC>(U + r0 * k, rows * k, ws);
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cl = lane & 15, q = lane >> 4;
+  const int row = 16 * w + cl;
+  d4 acc[KC];
+#pragma unroll
+  for (int bj = 0; bj < KC; ++bj)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rr = 16 * w + 4 * t + q, j = 16 * bj + cl;
+      acc[bj][t] = (rr < rows && j < k) ? ws[rr * k + j] : 0.0;
+    }
+  for (int l = 0; l < r; l += 4) {
+    const int lq = l + q;
+    const double a = (row < rows && lq < r) ? -zs[row * r + lq] : 0.0;
+#pragma unroll
+    for (int bj = 0; bj < KC; ++bj) {
+      const int j = 16 * bj + cl;
+      const double b = (lq < r && j < k) ? cm[lq * k + j] : 0.0;
+      acc[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[bj], 0, 0, 0);
+    }
+  }
+  // each W entry is read (above) and written (here) by the lane that owns it
+#pragma unroll
+  for (int bj = 0; bj < KC; ++bj)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rr = 16 * w + 4 * t + q, j = 16 * bj + cl;
+      if (rr < rows && j < k) ws[rr * k + j] = acc[bj][t];
+    }
+  __syncthreads();
+  gram_tile<KC>(ws, ws, rows, k, gpart + (int64_t)c * k * k);
+}
+
+// one workgroup: out = sqrt(lambda_max(G)) of the symmetric positive
+// semidefinite k x k G (repeated squaring); if hist != NULL also
+// hist[*ctr] = out, then ++*ctr.
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+sin_eig_kernel(int k, const double* __restrict__ Gin, double* __restrict__ out,
+               double* __restrict__ hist, int32_t* __restrict__ ctr) {
+  __shared__ double G[kMaxK * kMaxK];
+  __shared__ double B[kMaxK * kMaxK];
+  for (int e = threadIdx.x; e < k * k; e += kBlock) G[e] = Gin[e];
+  __syncthreads();
+  const double lam = lam_max_psd<KC>(G, B, k);
+  if (threadIdx.x == 0) {
+    const double v = sqrt(fmax(lam, 0.0));
+    if (out != nullptr) out[0] = v;
     if (hist != nullptr) {
       hist[*ctr] = v;
       *ctr = *ctr + 1;
@@ -1080,6 +1277,38 @@ hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* l
 hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const double* U,
                             double* out, double* hist, int32_t* ctr, hipStream_t s) {
   sin_theta_kernel<<<1, kBlock, 0, s>>>(d, r, k, Z, 0, 0, U, out, hist, ctr);
+  return hipGetLastError();
+}
+
+template <int KC>
+static void sin_theta_chunked_kc(int64_t d, int r, int k, const double* Z, const double* U,
+                                 double* scratch, double* out, double* hist, int32_t* ctr,
+                                 hipStream_t s) {
+  const int nch = nblk(d, kGramRows);
+  const int rk = r * k, kk = k * k;
+  double* cpart = scratch;
+  double* C = cpart + (int64_t)nch * rk;
+  double* gpart = C + rk;
+  double* G = gpart + (int64_t)nch * kk;
+  sin_cross_kernel<KC><<<nch, kBlock, 0, s>>>(d, r, k, Z, U, cpart);
+  sum_gram_kernel<<<dim3(nblk(rk, kBlock), 1), kBlock, 0, s>>>(nch, rk, cpart, C);
+  sin_resid_kernel<KC><<<nch, kBlock, 0, s>>>(d, r, k, Z, U, C, gpart);
+  sum_gram_kernel<<<dim3(nblk(kk, kBlock), 1), kBlock, 0, s>>>(nch, kk, gpart, G);
+  sin_eig_kernel<KC><<<1, kBlock, 0, s>>>(k, G, out, hist, ctr);
+}
+
+size_t sin_theta_scratch_doubles(int64_t d, int r, int k) {
+  const int64_t nch = (d + kGramRows - 1) / kGramRows;
+  return (size_t)((nch + 1) * ((int64_t)r * k + (int64_t)k * k));
+}
+
+hipError_t launch_sin_theta_chunked(int64_t d, int r, int k, const double* Z, const double* U,
+                                    double* scratch, double* out, double* hist, int32_t* ctr,
+                                    hipStream_t s) {
+  if (r <= 16) sin_theta_chunked_kc<1>(d, r, k, Z, U, scratch, out, hist, ctr, s);
+  else if (r <= 32) sin_theta_chunked_kc<2>(d, r, k, Z, U, scratch, out, hist, ctr, s);
+  else if (r <= 48) sin_theta_chunked_kc<3>(d, r, k, Z, U, scratch, out, hist, ctr, s);
+  else sin_theta_chunked_kc<4>(d, r, k, Z, U, scratch, out, hist, ctr, s);
   return hipGetLastError();
 }
 

@@ -144,6 +144,7 @@ bool make_plan(lp_dtype dtype, int64_t n, int64_t d, const int64_t* offsets, int
   L.rho = take(kHistCap * 8);
   L.rho_part = take(mb * 8);
   L.rho_ctr = take(4);
+  L.sinw = take(sin_theta_scratch_doubles(d, k_max, k_max) * 8);   // per-round sin theta
   // start and end stamps of every workgroup of one two-pass local multiply at the
   // default work-item size (pass 1: items x 128-row blocks, pass 2: items x
   // 256-column blocks)
@@ -230,7 +231,7 @@ using namespace lp;
 namespace {
 
 struct Ptrs {
-  double *Zi, *Yi, *Z, *Y, *Uref, *gram, *omat, *hist, *rho, *rho_part;
+  double *Zi, *Yi, *Z, *Y, *Uref, *gram, *omat, *hist, *rho, *rho_part, *sinw;
   void *Zw, *Zw_shared, *part, *tbuf;
   int8_t* sgn;
   int32_t *flags, *slot_off, *ctr, *rho_ctr;
@@ -251,6 +252,7 @@ Ptrs ptrs(lp_problem* P) {
   p.hist = (double*)(w + L.hist);
   p.rho = (double*)(w + L.rho);
   p.rho_part = (double*)(w + L.rho_part);
+  p.sinw = (double*)(w + L.sinw);
   p.rho_ctr = (int32_t*)(w + L.rho_ctr);
   p.Zw = w + L.Zw;
   p.Zw_shared = w + L.Zw_shared;
@@ -434,7 +436,7 @@ hipError_t enqueue_round_split(lp_problem* P, int k, int p, lp_agg mode, int his
   const hipStream_t s = st[0];
   LP_TRY(launch_aggregate_gram(P->m, d, k, q.Yi, 1.0 / (double)P->n, q.Y, q.gram, s));
   LP_TRY(cholqr2_from_gram(P->plan, P->ws, 1, d, k, q.Y, q.Z, q.Zw_shared, q.flags + P->m, s));
-  if (hist > 0) LP_TRY(launch_sin_theta(d, k, hist, q.Z, q.Uref, nullptr, q.hist, q.ctr, s));
+  if (hist > 0) LP_TRY(launch_sin_theta_chunked(d, k, hist, q.Z, q.Uref, q.sinw, nullptr, q.hist, q.ctr, s));
 #undef LP_TRY
   return hipSuccess;
 }
@@ -495,7 +497,7 @@ hipError_t enqueue_round(lp_problem* P, int k, int p, lp_agg mode, int hist) {
       hipSuccess)
     return e;
   if (hist > 0) {
-    if ((e = launch_sin_theta(d, k, hist, q.Z, q.Uref, nullptr, q.hist, q.ctr, s)) != hipSuccess) return e;
+    if ((e = launch_sin_theta_chunked(d, k, hist, q.Z, q.Uref, q.sinw, nullptr, q.hist, q.ctr, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -655,6 +657,11 @@ lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode) {
 }
 
 const double* drive_z(lp_problem* P) { return ptrs(P).Z; }
+
+hipError_t drive_change(lp_problem* P, int k, const double* Zprev, double* out) {
+  Ptrs q = ptrs(P);
+  return launch_sin_theta_chunked(P->d, k, k, q.Z, Zprev, q.sinw, out, nullptr, nullptr, P->stream);
+}
 
 lp_status report(lp_status s, const std::string& msg) { return fail(s, msg); }
 
@@ -1208,7 +1215,7 @@ lp_status lp_solve(lp_problem* P, int32_t k, lp_agg mode, const double* Y0, doub
   while (rounds < o.max_rounds && !settled) {
     const int p = rule.p;
     if ((st = run_round(P, k, p, mode, 0, true, -1)) != LP_OK) return st;
-    LP_HIP(launch_sin_theta(P->d, k, k, q.Z, q.Uref, q.hist, nullptr, nullptr, s));
+    LP_HIP(launch_sin_theta_chunked(P->d, k, k, q.Z, q.Uref, q.sinw, q.hist, nullptr, nullptr, s));
     LP_HIP(hipMemcpyAsync(q.Uref, q.Z, dk * 8, hipMemcpyDeviceToDevice, s));
     LP_HIP(hipMemcpyAsync(P->change_host, q.hist, sizeof(double), hipMemcpyDeviceToHost, s));
     LP_HIP(hipStreamSynchronize(s));

@@ -33,7 +33,7 @@ enum class LocalPath : int { TwoPass = 0, Mfma32 = 1, MfmaBf16 = 2 };
 struct Layout {
   // byte offsets into the workspace
   size_t Zi, Zw, Yi, tmp, Z, Zw_shared, Y, Uref, part, tbuf, gram, gram2, rinv, omat, sgn, flags,
-      items, slot_off, hist, ctr, scal, rho, rho_part, rho_ctr, stamps, total;
+      items, slot_off, hist, ctr, scal, rho, rho_part, rho_ctr, sinw, stamps, total;
 };
 
 constexpr int kHistCap = 1024;  // rounds of sin-theta history buffered on the device
@@ -151,6 +151,9 @@ namespace lp {
 lp_status drive_begin(lp_problem* P, int k, const double* Y0, bool orthonormal);
 lp_status drive_round(lp_problem* P, int k, int p, lp_agg mode);
 const double* drive_z(lp_problem* P);
+// out (device) = sin theta_k(drive_z, Zprev), enqueued on drive_stream(P) with the
+// problem's own scratch (the change of a round).
+hipError_t drive_change(lp_problem* P, int k, const double* Zprev, double* out);
 hipStream_t drive_stream(lp_problem* P);
 lp_status drive_breakdowns(lp_problem* P, int* breakdowns);
 // BF16 operand pairs in the fused BF16 kernel (lp_tuning.split_operands) without
@@ -285,6 +288,14 @@ hipError_t launch_sym_eig(int nchunks, int k, const double* gram_part, double* l
 // hist[*ctr] then increments *ctr.
 hipError_t launch_sin_theta(int64_t d, int r, int k, const double* Z, const double* U,
                             double* out, double* hist, int32_t* ctr, hipStream_t s);
+// The same distance with the O(d r k) work spread over ceil(d / 64) workgroups
+// (five launches; the per-round form): scratch holds sin_theta_scratch_doubles
+// FP64 values (the chunk partials of Z^T U and of the residual's Gram, and
+// their sums).
+size_t sin_theta_scratch_doubles(int64_t d, int r, int k);
+hipError_t launch_sin_theta_chunked(int64_t d, int r, int k, const double* Z, const double* U,
+                                    double* scratch, double* out, double* hist, int32_t* ctr,
+                                    hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t s);
 

@@ -3,7 +3,7 @@
 // One worker thread owns all GPU work.  Jobs wait in a FIFO until their
 // device footprint fits the budget and a slot is free (admission); an
 // admitted job gets a slot (a stream for its allocations and a pinned change
-// cell), one stream-ordered allocation for its workspace and small buffers,
+// cell), a range of the server's device arena for its workspace and buffers,
 // and an lp_problem with its own stream.  The worker keeps one round in
 // flight per job: a round, the change sin theta(Z_r, Z_{r-1}) into pinned
 // memory and an event; it polls the events, applies the per-job stop rule,
@@ -16,9 +16,11 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 
+#include "arena.h"
 #include "lp_internal.h"
 
 namespace {
@@ -43,6 +45,7 @@ struct Job {
   // set at admission
   int slot = -1;
   char* mem = nullptr;
+  size_t arena_off = 0, arena_bytes = 0;   // the job's range of the server's arena
   lp_problem* P = nullptr;
   double* y0_dev = nullptr;
   double* zprev = nullptr;
@@ -71,6 +74,11 @@ struct lp_server {
   std::vector<hipEvent_t> slot_event;
   std::vector<int> free_slots;
   double* pinned = nullptr;   // one change cell per slot
+  // the jobs' device memory: one arena of the budget, allocated with the server;
+  // a job is admitted when a range of its footprint is free (per-job allocations
+  // from a stream-ordered pool left the GPU idle for 0.1-1.4 s at some
+  // admissions once the pool had grown over many job sizes)
+  lp::Arena arena;
   std::thread worker;
 };
 
@@ -142,11 +150,17 @@ void publish(lp_server* S, Job* j, lp_status st) {
 void release(lp_server* S, Job* j) {
   if (j->P != nullptr) (void)lp_destroy(j->P);
   j->P = nullptr;
-  if (j->mem != nullptr) (void)hipFreeAsync(j->mem, S->slot_stream[j->slot]);
+  if (j->arena_bytes > 0) {
+    // the job's range is reused by the next admission: nothing of this job may
+    // still run on its slot stream (its problem stream was synchronised)
+    if (j->slot >= 0) (void)hipStreamSynchronize(S->slot_stream[j->slot]);
+    S->arena.give(j->arena_off, j->arena_bytes);
+  }
+  j->arena_bytes = 0;
   j->mem = nullptr;
   if (j->ready != nullptr) (void)hipEventDestroy(j->ready);
   j->ready = nullptr;
-  S->free_slots.push_back(j->slot);
+  if (j->slot >= 0) S->free_slots.push_back(j->slot);
   j->slot = -1;
 }
 
@@ -173,8 +187,7 @@ lp_status launch(lp_server* S, Job* j) {
   const int64_t dk = j->spec.d * j->spec.k;
   lp_status st = lp::drive_round(P, j->spec.k, j->rule.p, j->spec.mode);
   if (st != LP_OK) return st;
-  if (lp::launch_sin_theta(j->spec.d, j->spec.k, j->spec.k, lp::drive_z(P), j->zprev, j->change_dev, nullptr,
-                           nullptr, s) != hipSuccess ||
+  if (lp::drive_change(P, j->spec.k, j->zprev, j->change_dev) != hipSuccess ||
       hipMemcpyAsync(j->zprev, lp::drive_z(P), dk * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(S->pinned + j->slot, j->change_dev, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipEventRecord(S->slot_event[j->slot], s) != hipSuccess)
@@ -192,10 +205,7 @@ lp_status start(lp_server* S, Job* j) {
   // everything the caller queued on its stream before the submit comes first
   if (hipStreamWaitEvent(ss, j->ready, 0) != hipSuccess)
     return lp::report(LP_EDEVICE, "serving: wait for the caller's stream failed");
-  if (hipMallocAsync((void**)&j->mem, j->footprint, ss) != hipSuccess) {
-    j->mem = nullptr;
-    return lp::report(LP_EDEVICE, "serving: allocation failed");
-  }
+  j->mem = S->arena.base + j->arena_off;
   lp_job& sp = j->spec;
   if (j->a_bytes > 0) {
     // the job's own matrix, generated at admission after the buffers it uses
@@ -270,10 +280,15 @@ void worker_main(lp_server* S) {
         S->queue.clear();
         if (S->active.empty()) break;
       }
-      // a job is admitted only with a slot reserved for it (slots are taken in start())
-      while (!S->queue.empty() && admitted.size() < S->free_slots.size() &&
-             S->used + S->queue.front()->footprint <= S->budget) {
+      // a job is admitted only with a slot reserved for it (slots are taken in
+      // start()) and a range of the arena for its footprint (FIFO: the head waits
+      // until one is free; with no job active the whole arena is, and every
+      // footprint fits the budget)
+      while (!S->queue.empty() && admitted.size() < S->free_slots.size()) {
         Job* j = S->queue.front();
+        const size_t bytes = round_up(j->footprint, 256);
+        if (!S->arena.take(bytes, &j->arena_off)) break;
+        j->arena_bytes = bytes;
         S->queue.pop_front();
         S->used += j->footprint;
         admitted.push_back(j);
@@ -288,8 +303,7 @@ void worker_main(lp_server* S) {
       lp_status st = start(S, j);
       if (st != LP_OK) {
         if (j->P != nullptr) (void)hipStreamSynchronize(lp::drive_stream(j->P));
-        if (j->slot >= 0) release(S, j);
-        else if (j->ready != nullptr) (void)hipEventDestroy(j->ready);
+        release(S, j);
         publish(S, j, st);
         delete j;
         continue;
@@ -347,6 +361,14 @@ lp_status lp_server_create(lp_server** out, size_t hbm_budget_bytes, int32_t max
     delete S;
     return lp::report(LP_EDEVICE, "serving: device or pinned memory unavailable");
   }
+  S->arena.size = round_up(hbm_budget_bytes, 256);
+  if (hipMalloc((void**)&S->arena.base, S->arena.size) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(S->pinned);
+    delete S;
+    return lp::report(LP_ENOMEM, "serving: the budget does not fit in free device memory");
+  }
+  S->arena.free_ranges.emplace(0, S->arena.size);
   S->slot_stream.assign(max_active, nullptr);
   S->slot_event.assign(max_active, nullptr);
   for (int i = 0; i < max_active; ++i) {
@@ -356,6 +378,7 @@ lp_status lp_server_create(lp_server** out, size_t hbm_budget_bytes, int32_t max
         if (S->slot_stream[t]) (void)hipStreamDestroy(S->slot_stream[t]);
         if (S->slot_event[t]) (void)hipEventDestroy(S->slot_event[t]);
       }
+      (void)hipFree(S->arena.base);
       (void)hipHostFree(S->pinned);
       delete S;
       return lp::report(LP_EDEVICE, "serving: stream creation failed");
@@ -440,6 +463,9 @@ lp_status lp_server_destroy(lp_server* S) {
     (void)hipStreamDestroy(S->slot_stream[i]);
     (void)hipEventDestroy(S->slot_event[i]);
   }
+  // every slot stream has been synchronised above, and every problem stream when
+  // its job ended
+  (void)hipFree(S->arena.base);
   (void)hipHostFree(S->pinned);
   delete S;
   return LP_OK;
