@@ -590,6 +590,24 @@ lp_status join_out(lp_problem* P) {
 }
 
 // Copy the work list and the per-partition slot prefix to the device (synchronous).
+// The two-pass kernels write one d x k partial per work item, read back by the
+// reduction; one workgroup per item matters only to the fused kernels.  When the
+// problem's rank runs two-pass, items of 16 k acc / b rows keep the partials
+// under 1/16 of A's bytes, as long as items x ceil(d / 256) pass-2 workgroups
+// still cover the chip (512).  (At d = 4096, n = 65536, k = 64 in BF16 the
+// default items wrote as many partial bytes as A holds.)  Returns whether the
+// work list changed (it then needs an upload).
+bool two_pass_items(lp_problem* P) {
+  if (fused_for_k(P, P->k_max)) return false;
+  const int64_t b = P->dtype == LP_F64 ? 8 : (P->dtype == LP_F32 ? 4 : 2);
+  int64_t cr = std::min<int64_t>(16 * (int64_t)P->k_max * (int64_t)P->plan.acc_bytes / b,
+                                 P->n * ((P->d + 255) / 256) / 512);
+  cr = std::min<int64_t>(cr / 16 * 16, 4096);
+  if (cr <= P->plan.chunk_rows) return false;
+  build_items(&P->plan, P->offsets.data(), cr);
+  return true;
+}
+
 lp_status upload_items(lp_problem* P) {
   const int m = P->m;
   std::vector<int32_t> slot_off(m + 1, 0);
@@ -667,10 +685,12 @@ lp_status report(lp_status s, const std::string& msg) { return fail(s, msg); }
 
 hipStream_t drive_stream(lp_problem* P) { return P->stream; }
 
-void drive_split_operands(lp_problem* P, bool split) {
+lp_status drive_split_operands(lp_problem* P, bool split) {
   P->plan.split_operands = split;
   for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
   P->graphs.clear();
+  // split operands at k > 16, d = 2048 move the rank to the two-pass kernels
+  return two_pass_items(P) ? upload_items(P) : LP_OK;
 }
 
 lp_status drive_breakdowns(lp_problem* P, int* breakdowns) {
@@ -746,6 +766,7 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
   P->plan.path = fused_kind(P);
   if (P->plan.path == LocalPath::MfmaBf16) P->plan.variant = 0;
   P->offsets.assign(offsets, offsets + m + 1);
+  two_pass_items(P);
   P->base = 0;
   for (int i = 1; i < m; ++i)
     if (offsets[i + 1] - offsets[i] > offsets[P->base + 1] - offsets[P->base]) P->base = i;

@@ -156,9 +156,10 @@ const double* drive_z(lp_problem* P);
 hipError_t drive_change(lp_problem* P, int k, const double* Zprev, double* out);
 hipStream_t drive_stream(lp_problem* P);
 lp_status drive_breakdowns(lp_problem* P, int* breakdowns);
-// BF16 operand pairs in the fused BF16 kernel (lp_tuning.split_operands) without
-// the synchronising re-upload of lp_set_tuning (for a problem with no rounds yet).
-void drive_split_operands(lp_problem* P, bool split);
+// BF16 operand pairs in the fused BF16 kernel (lp_tuning.split_operands) for a
+// problem with no rounds yet, without lp_set_tuning's re-tuning; the work list
+// is uploaded again (synchronising) only when the rank moves to the two-pass kernels.
+lp_status drive_split_operands(lp_problem* P, bool split);
 // Record msg as the thread's last error (lp_last_error) and return s.
 lp_status report(lp_status s, const std::string& msg);
 
