@@ -350,7 +350,7 @@ def serve_run(lp, synth, jobs, dtype, rate, max_active, budget, seed, truth):
 
 def serve_main(args):
     """Serving: the same seeded job list in two legs at every arrival rate: all FP32
-    one job at a time (the plain per-job path) and all BF16 batched (16 active,
+    one job at a time (the plain per-job path) and all BF16 batched (--max-active, 16 by default,
     continuous batching).  Every job must end within 1e-4 of its exact subspace."""
     import synth
     import paper_2002_08014_amd as lp
@@ -366,7 +366,7 @@ def serve_main(args):
     torch.cuda.synchronize()
     elems = sum(j["n"] * j["d"] for j in jobs)
     budget = 160 << 30
-    legs = {"fp32_one_at_a_time": (torch.float32, 1), "bf16_batched": (torch.bfloat16, 16)}
+    legs = {"fp32_one_at_a_time": (torch.float32, 1), "bf16_batched": (torch.bfloat16, args.max_active)}
     runs = {leg: [] for leg in legs}
     for rate in args.rates:
         for leg, (dtype, active) in legs.items():
@@ -633,6 +633,8 @@ def main():
     ap.add_argument("--workload", default=None, choices=sorted(WORKLOADS) + ["serve"],
                     help="one workload alone (default: the headline plus the sub-records)")
     ap.add_argument("--jobs", type=int, default=200, help="serving: jobs per arrival rate")
+    ap.add_argument("--max-active", type=int, default=16,
+                    help="serving: jobs admitted at once in the batched BF16 leg")
     ap.add_argument("--rates", type=float, nargs="*", default=[10.0, 25.0, 50.0, 100.0, 200.0, 500.0],
                     help="serving: Poisson arrival rates (jobs/s)")
     ap.add_argument("--rounds", type=int, default=0, help="override the workload's round count")
