@@ -116,8 +116,12 @@ lp_status lp_destroy(lp_problem* P);
  *                 4 and 5 the same with two tiles in flight per wave.
  *                 With local_kernel 0, ranks k <= 8 (FP32 or BF16 A, d a power of two in
  *                 [256, 4096]) run a fused vector-ALU kernel (A read once, FP32
- *                 arithmetic, no matrix cores); naming a kernel (1..11) runs that one.
- *                 Other shapes and ranks use the two-pass kernel.
+ *                 arithmetic, no matrix cores), other ranks of the fused shapes the fused
+ *                 matrix-core kernel in its default form (FP32: 9; BF16: 2); naming a
+ *                 kernel (1..11) runs that one.  Other shapes and ranks use the two-pass
+ *                 kernel.  (The serving layer, which does not autotune, runs ranks 5..8
+ *                 of FP32 and 1..8 of BF16 A on the fused matrix-core kernel where one
+ *                 takes the shape: measured faster there.)
  *                 11: the two-pass kernel on BF16 matrix cores: every FP32 operand (A,
  *                 Z_i, t) split exactly into three BF16 pieces and the six leading
  *                 partial products summed in FP32 (dropped terms below 2^-23 of each

@@ -685,6 +685,13 @@ lp_status report(lp_status s, const std::string& msg) { return fail(s, msg); }
 
 hipStream_t drive_stream(lp_problem* P) { return P->stream; }
 
+void drive_prefer_matrix_cores(lp_problem* P, int k) {
+  const bool bf16 = P->dtype == LP_BF16 &&
+                    mfma16_eligible(P->dtype, P->d, P->lda, k, P->A, P->plan.split_operands);
+  const bool fp32 = P->dtype == LP_F32 && k >= 5 && mfma32_eligible(P->dtype, P->d, P->lda, k);
+  if (k <= 8 && (bf16 || fp32)) P->plan.valu = false;
+}
+
 lp_status drive_split_operands(lp_problem* P, bool split) {
   P->plan.split_operands = split;
   for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -764,6 +771,10 @@ lp_status lp_create(lp_problem** out, const void* A, lp_dtype dtype, int64_t n, 
   P->m = m;
   P->k_max = k_max;
   P->plan.path = fused_kind(P);
+  // untuned defaults: the fused variants the autotuner picks on the benchmark shapes
+  // (FP32: direct-to-LDS, software-pipelined, public local_kernel 9; BF16: four
+  // waves, one tile ahead, public 2)
+  if (P->plan.path == LocalPath::Mfma32) P->plan.variant = 7;
   if (P->plan.path == LocalPath::MfmaBf16) P->plan.variant = 0;
   P->offsets.assign(offsets, offsets + m + 1);
   two_pass_items(P);
@@ -842,7 +853,7 @@ lp_status lp_set_tuning(lp_problem* P, const lp_tuning* t) {
     P->plan.path = LocalPath::TwoPass;
   } else if (fk == LocalPath::Mfma32) {
     P->plan.path = fk;
-    P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 1;
+    P->plan.variant = t->local_kernel >= 2 ? t->local_kernel - 2 : 7;   // automatic: the default
   } else if (fk == LocalPath::MfmaBf16) {
     P->plan.path = fk;
     const bool w8 = P->d == 1024 || P->d == 2048;   // the eight-wave forms need these widths

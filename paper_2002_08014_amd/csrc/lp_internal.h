@@ -160,6 +160,12 @@ lp_status drive_breakdowns(lp_problem* P, int* breakdowns);
 // problem with no rounds yet, without lp_set_tuning's re-tuning; the work list
 // is uploaded again (synchronising) only when the rank moves to the two-pass kernels.
 lp_status drive_split_operands(lp_problem* P, bool split);
+// Ranks up to 8 where the zero-padded fused matrix-core kernel measured faster than
+// the vector-ALU kernel: BF16 A (0.88 of the HBM peak at k = 4 and 8, 1048576 x 2048,
+// against about 0.5) and FP32 A at k >= 5 (180 against 204 us at k = 8, 262144 x
+// 1024; k = 4 stays on the vector-ALU kernel, 166 us).  For a served job, which is
+// not autotuned; call before its first round.
+void drive_prefer_matrix_cores(lp_problem* P, int k);
 // Record msg as the thread's last error (lp_last_error) and return s.
 lp_status report(lp_status s, const std::string& msg);
 

@@ -223,6 +223,7 @@ lp_status start(lp_server* S, Job* j) {
   }
   if (sp.dtype == LP_BF16 && (st = lp::drive_split_operands(j->P, sp.single_bf16 == 0)) != LP_OK)
     return st;
+  lp::drive_prefer_matrix_cores(j->P, sp.k);
   const size_t dk8 = round_up((size_t)sp.d * sp.k * 8, 256);
   j->y0_dev = (double*)(j->mem + j->ws_bytes);
   j->zprev = (double*)(j->mem + j->ws_bytes + dk8);

@@ -137,8 +137,13 @@ def test_served_generated_job(lp, dtype, d, k, m):
     # the same job alone through lp_solve on the same generated matrix and start
     A, _ = lp.lp_generate(n, d, k, 1.2, 0.97, seed, dtype=dtype, basis=False)
     P = lp.lp_create(A, offs, k)
+    # the server's kernel choice: BF16 jobs use operand pairs; ranks up to 8 run the
+    # fused matrix-core kernel where one takes the shape (FP32 from k = 5)
     if dtype == torch.bfloat16:
-        lp.lp_set_tuning(P, 0, 0, False, True)     # served BF16 jobs use operand pairs
+        fused_bf16 = k <= 8 and d in (512, 1024, 1536, 2048)
+        lp.lp_set_tuning(P, 2 if fused_bf16 else 0, 0, False, True)
+    elif 5 <= k <= 8 and d in (256, 512, 768, 1024):
+        lp.lp_set_tuning(P, 9, 0)
     alone = lp.lp_solve(P, k, "sign", None, 4, 1e-5, 300, seed=seed)
     assert alone["stats"]["rounds"] == r["rounds"]
     assert torch.equal(alone["Z"], r["Z"])
