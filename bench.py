@@ -284,7 +284,7 @@ def trends(lp, synth, w, k, rounds=40, ms=(8, 32, 128), ps=(1, 2, 4, 8, 16)):
 
 
 def make_job_mix(n_jobs, seed):
-    """Seeded serving job list (survey mix): d in {256, 512, 1024, 2048, 4096},
+    """Seeded serving job list (the serving configuration): d in {256, 512, 1024, 2048, 4096},
     n = B d with B uniform in [16, 256], k in {4, 8, 16, 32, 64} (k <= d), m in
     {4, 16, 64} equal partitions, sign or OPT alignment, p0 = 4, target 1e-4.  Each
     job's A is the exact-truth matrix (lp_generate: gap 1.2 after sigma_k, decay 0.97)
