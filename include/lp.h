@@ -136,9 +136,12 @@ lp_status lp_destroy(lp_problem* P);
  *                 t = A Z once to BF16 (a sin theta floor near 1e-3 against FP64 on the
  *                 same values, within the BF16 tolerance of 2e-2).  1: each operand is a
  *                 pair hi = bf16(x), lo = bf16(x - hi) and every product is taken twice,
- *                 FP32-class results for twice the matrix-core work; at k > 16, d = 2048
- *                 (the pairs do not fit a CU's registers) the two-pass kernel with FP32
- *                 operands runs instead.  The autotuner keeps this setting. */
+ *                 FP32-class results for twice the matrix-core work.  Where no fused
+ *                 kernel takes the shape (and at k > 16, d = 2048, where the pairs do not
+ *                 fit a CU's registers), local_kernel 0 runs the two-pass kernel on BF16
+ *                 matrix cores with Z_i and t as the same pairs (two BF16 products per
+ *                 FP32 product instead of three); a named two-pass kernel (1 or 11) keeps
+ *                 its own operands.  The autotuner keeps this setting. */
 typedef struct {
   int32_t struct_size;
   int32_t local_kernel;

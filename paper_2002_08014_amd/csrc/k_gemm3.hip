@@ -108,13 +108,16 @@ __device__ inline void split4(f4 x, bf4 (&o)[NP]) {
   for (int q = 0; q < NP; ++q) o[q] = __builtin_bit_cast(bf4, uint2{u[0][q], u[1][q]});
 }
 
-// acc += x y over the kept terms x_a y_b, a + b <= 2 (x has PA pieces, y three)
-template <int PA>
+// acc += x y over the kept terms x_a y_b, a + b <= 2 (x has PA pieces, y three).
+// YT = 2 (BF16 x only: operand pairs) drops x_0 y_2 as well: y is then carried by
+// its first two pieces, within 2^-16 of itself.
+template <int PA, int YT>
 __device__ inline f4 mfma_terms(const bf8 (&x)[PA], const bf8 (&y)[3], f4 acc) {
+  static_assert(YT == 3 || (YT == 2 && PA == 1), "operand pairs only with BF16 A");
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[1], acc, 0, 0, 0);
   if constexpr (PA > 1) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], acc, 0, 0, 0);
+  if constexpr (YT == 3) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], acc, 0, 0, 0);
   if constexpr (PA > 1) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[1], acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], y[0], acc, 0, 0, 0);
@@ -126,7 +129,7 @@ __device__ inline f4 mfma_terms(const bf8 (&x)[PA], const bf8 (&y)[3], f4 acc) {
 // 4 waves, wave w owns rows 32 w .. 32 w + 31 of the block (MT = 2 16-row blocks).
 // A goes from HBM straight into registers, PF slices ahead; the Z_i slice is
 // split into its three pieces once per workgroup and staged in LDS (two buffers).
-template <typename TA, int NT, int PF>
+template <typename TA, int NT, int PF, int YT>
 __global__ void __launch_bounds__(256)
 tmm3_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ Zw,
             int64_t z_stride, const WorkItem* __restrict__ items, float* __restrict__ t,
@@ -236,7 +239,7 @@ tmm3_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float
 #pragma unroll
       for (int p = 0; p < 3; ++p) zp[p] = *(const bf8*)&Zs[b][p][(16 * nt + i) * kZR + 8 * g];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_terms<PA>(ap[mt], zp, acc[mt][nt]);
+      for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_terms<PA, YT>(ap[mt], zp, acc[mt][nt]);
     }
     if (s + 1 < nsl) stash_z(b ^ 1, c0 + kBK);
     __syncthreads();
@@ -287,7 +290,7 @@ __device__ inline int aoff(int r, int u) {
 // A slices come into registers PF slices ahead, each wave splits its own 32 x 64
 // block into LDS (no other wave reads it); the t slice is split once per
 // workgroup into two LDS buffers.
-template <typename TA, int NT, int PF>
+template <typename TA, int NT, int PF, int YT>
 __global__ void __launch_bounds__(256)
 ymm3_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float* __restrict__ t,
             const WorkItem* __restrict__ items, float* __restrict__ part,
@@ -405,7 +408,7 @@ ymm3_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float
         ap[p] = __builtin_bit_cast(bf8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
       }
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_terms<PA>(ap, tp[nt], acc[mt][nt]);
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_terms<PA, YT>(ap, tp[nt], acc[mt][nt]);
     }
   };
 
@@ -440,30 +443,30 @@ ymm3_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int k, const float
   }
 }
 
-template <typename TA, int NT>
+template <typename TA, int NT, int YT>
 hipError_t pair3(const Plan& P, const void* A, int64_t lda, int k, const void* Zw, int64_t z_stride,
                  void* tbuf, void* part, const WorkItem* items, int nitems, hipStream_t s) {
   dim3 g1(nitems, (unsigned)((P.chunk_rows + kBM1 - 1) / kBM1));
   unsigned long long* st1 = P.stamps;
   unsigned long long* st2 = P.stamps != nullptr ? P.stamps + 2 * (int64_t)g1.x * g1.y : nullptr;
-  tmm3_kernel<TA, NT, kPF1><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)Zw, z_stride,
+  tmm3_kernel<TA, NT, kPF1, YT><<<g1, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)Zw, z_stride,
                                          items, (float*)tbuf, st1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 g2(nitems, (unsigned)((P.d + 4 * kWC - 1) / (4 * kWC)));
-  ymm3_kernel<TA, NT, kPF2><<<g2, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)tbuf, items,
+  ymm3_kernel<TA, NT, kPF2, YT><<<g2, 256, 0, s>>>((const TA*)A, lda, P.d, k, (const float*)tbuf, items,
                                          (float*)part, st2);
   return hipGetLastError();
 }
 
-template <typename TA>
+template <typename TA, int YT>
 hipError_t pair3_k(const Plan& P, const void* A, int64_t lda, int k, const void* Zw,
                    int64_t z_stride, void* tbuf, void* part, const WorkItem* items, int nitems,
                    hipStream_t s) {
-  if (k <= 16) return pair3<TA, 1>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
-  if (k <= 32) return pair3<TA, 2>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
-  if (k <= 48) return pair3<TA, 3>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
-  return pair3<TA, 4>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  if (k <= 16) return pair3<TA, 1, YT>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  if (k <= 32) return pair3<TA, 2, YT>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  if (k <= 48) return pair3<TA, 3, YT>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  return pair3<TA, 4, YT>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
 }
 
 }  // namespace
@@ -472,8 +475,13 @@ hipError_t launch_local_multiply_gemm3(const Plan& P, const void* A, int64_t lda
                                        const void* Zw, int64_t z_stride, void* tbuf, void* part,
                                        const WorkItem* items, int nitems, hipStream_t s) {
   if (P.dtype == LP_F32)
-    return pair3_k<float>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
-  return pair3_k<__hip_bfloat16>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+    return pair3_k<float, 3>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  // BF16 A with operand pairs asked for (split_operands) and no kernel named: Z_i and
+  // t carried by two BF16 pieces each, the precision of the fused kernel's pairs,
+  // for two products instead of three
+  if (P.split_operands && P.two_pass_auto && !P.split_products)
+    return pair3_k<__hip_bfloat16, 2>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
+  return pair3_k<__hip_bfloat16, 3>(P, A, lda, k, Zw, z_stride, tbuf, part, items, nitems, s);
 }
 
 void two_pass_geometry(const Plan& P, int64_t* rows_per_wg1, int64_t* cols_per_wg2) {

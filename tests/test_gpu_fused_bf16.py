@@ -176,6 +176,30 @@ def test_bf16_split_operands_small(lp, d, k, variant):
         _check_split(Y, upcast(A_dev), w.offsets, Zw, range(m))
 
 
+@pytest.mark.parametrize("d,k", [(256, 16), (2048, 24), (4096, 64)])
+def test_bf16_pairs_on_the_two_pass_kernel(lp, d, k):
+    """Operand pairs with no kernel named, on shapes no fused kernel takes: the
+    two-pass kernel on BF16 matrix cores carries Z_i and t as hi/lo BF16 pairs (two
+    products per FP32 product).  A pair leaves |x - hi - lo| <= u_b^2 |x| (two
+    round-to-nearest steps to 8 bits), so each entry obeys
+      |Y - A^T A Z| <= (2 u_b^2 + (d + s + 4) u_32)(1 + 4 u_b) |A|^T (|A| |Z|)."""
+    print(f"bf16 pairs two-pass d={d} k={k}", flush=True)
+    n, m = 3 * d + 37, 3
+    w = synth.make_small(n, d, k, m, seed=d + k + 3, dtype=torch.bfloat16, uneven=True)
+    A_dev = w.A.to("cuda:0")
+    P = lp.lp_create(A_dev, w.offsets, k)
+    lp.lp_set_tuning(P, 0, 0, False, True)
+    Z = oracle.orth(np.random.default_rng(d + k + 3).standard_normal((d, k)))
+    Y = host(lp.lp_local_multiply(P, k, torch.as_tensor(Z)))
+    Zw = Z.astype(np.float32).astype(np.float64)
+    A = upcast(A_dev)
+    for i in range(m):
+        Ai = A[w.offsets[i]:w.offsets[i + 1]]
+        bound = np.abs(Ai).T @ (np.abs(Ai) @ np.abs(Zw))
+        gamma = (2 * U_B ** 2 + (d + Ai.shape[0] + 4) * U_32) * (1 + 4 * U_B)
+        assert np.all(np.abs(Y[i] - Ai.T @ (Ai @ Zw)) <= gamma * bound)
+
+
 def test_bf16_split_operands_run_parity(lp):
     """A whole run with operand pairs (d = 1024, k = 16) is FP32-class: within
     1e-5 of the oracle on the same BF16 values (single roundings sit near 1e-3)."""
