@@ -53,3 +53,16 @@ def rule_schedule(changes, p0, target):
         if p > 1 and (settled or q > 0.5):
             p, prev_c, prev_q = max(1, p // 2), -1.0, -1.0
     return ps, False
+
+
+CAPTURE = None   # pytest's capture manager, set by conftest.py
+
+
+def progress(msg: str) -> None:
+    """Print a progress line of a long step on the real stdout, past pytest's
+    capture (plain print when there is no capture manager)."""
+    if CAPTURE is not None:
+        with CAPTURE.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)

@@ -10,6 +10,10 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    # progress lines of long steps (the full-size oracle runs) go to the real
+    # stdout even while pytest captures the test's output
+    from tests import _util
+    _util.CAPTURE = config.pluginmanager.getplugin("capturemanager")
 
 
 @pytest.fixture(scope="session")

@@ -32,13 +32,13 @@ import torch
 
 import oracle
 import synth
-from tests._util import host, sign_normalise, sin_theta_np
+from tests._util import host, progress, sign_normalise, sin_theta_np
 
 pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
+    progress(msg)
 
 
 @pytest.fixture(scope="module")
